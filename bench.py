@@ -1,0 +1,160 @@
+"""Benchmark: BRDF solves per second (Fourier orders x incident directions) on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload particulate] [--no-cpu-baseline]
+
+A step is one full solve of the workload (all stages: Legendre matrices and E/F assembly, FE
+product, eigen-decomposition, mode vectors, boundary solves, emergent response and Fourier
+synthesis of F_r) with the inputs already resident in device memory. The unit count of a layer is
+M x N x n_dphi (orders x incident zenith nodes x incident azimuths). Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector and FP64 matrix
+PEAK_HBM_GBS = 8000.0
+
+
+def stage_work(stage, layers):
+    """Algorithmic work of one launch of `stage` over all (layer, order) items.
+
+    Returns (bound, amount, unit) with amount in flops (alu/mfma) or bytes (hbm)."""
+    fl = 0.0
+    by = 0.0
+    for N, L, M, P in zip(layers.N, layers.L, layers.M, layers.n_dphi):
+        n = 4 * N
+        for m in range(M):
+            if stage == "eigen":
+                fl += 25.0 * n ** 3           # real Schur form + eigenvectors (Golub-Van Loan count)
+            elif stage in ("gemm_FE", "gemm_U", "gemm_V"):
+                fl += 2.0 * n ** 3
+            elif stage == "rdiv":
+                fl += 2 * (2.0 / 3.0 * n ** 3 + 2.0 * n ** 3)  # two LU + two n-RHS right divisions
+            elif stage == "assemble":
+                fl += N * N * (L - m) * 72.0  # 36 products-with-coefficient per degree and block pair
+        if stage == "synth":
+            by += 8.0 * (M * n * n + N * N * P * 16)
+    if stage == "synth":
+        return "hbm", by, "GB/s"
+    if stage in ("gemm_FE", "gemm_U", "gemm_V"):
+        return "mfma", fl, "TFLOP/s"
+    return "alu", fl, "TFLOP/s"
+
+
+def cpu_baseline(layers, units):
+    from threadpoolctl import threadpool_info
+
+    from oracle import dom
+
+    t0 = time.perf_counter()
+    for i in range(layers.n_layers):
+        dom.brdf(layers.coef[i], layers.tau[i], layers.omega[i], layers.N[i], layers.M[i], layers.n_dphi[i])
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": units / dt, "unit": "BRDF solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one full solve of the workload ({layers.n_layers} layer(s)), {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="particulate")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (orders and layers are "
+              "independent, so a multi-GPU run would shard them; that path is not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1707_05882_amd import binding
+    from paper_1707_05882_amd.api import pack_coefficients
+    from workloads import workload
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    layers = workload(args.workload)
+    units = layers.units()
+    plan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, flags=binding.FLAG_STAGE_TIMING)
+    tau = torch.as_tensor(layers.tau, device=dev)
+    omega = torch.as_tensor(layers.omega, device=dev)
+    coef = torch.as_tensor(pack_coefficients(layers.coef), device=dev)
+    F = torch.empty(plan.output_bytes() // 8, dtype=torch.float64, device=dev)
+    status = torch.empty(layers.n_layers, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        plan.solve(tau, omega, coef, F, status, stream.cuda_stream)
+    torch.cuda.synchronize()
+    if args.warmup:
+        plan.stage_times()  # discard warm-up events
+    st = status.cpu().numpy()
+    if np.any(st != 0):
+        print(f"solve failed: layer status {st.tolist()}", file=sys.stderr)
+        sys.exit(1)
+
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(args.steps):
+        plan.solve(tau, omega, coef, F, status, stream.cuda_stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    stages = plan.stage_times()
+    ms = total_ms / args.steps
+    if np.any(status.cpu().numpy() != 0) or not torch.isfinite(F).all():
+        print("solve failed during the timed region", file=sys.stderr)
+        sys.exit(1)
+
+    dom_stage = max(stages, key=stages.get)
+    bound, work, unit = stage_work(dom_stage, layers)
+    dur_s = stages[dom_stage] / 1e3
+    if bound == "hbm":
+        achieved, peak = work / dur_s / 1e9, PEAK_HBM_GBS
+    else:
+        achieved, peak = work / dur_s / 1e12, PEAK_FP64_TFLOPS
+    roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+                "traffic": None, "kernel": f"k_{dom_stage.split('_')[0]}" if dom_stage.startswith("gemm") else f"k_{dom_stage}",
+                "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
+
+    out = {
+        "metric": "BRDF solves/sec (orders x incident dirs)",
+        "value": units / (ms / 1e3),
+        "unit": "BRDF solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": layers.name, "layers": layers.n_layers, "N": layers.N[0] if layers.n_layers == 1 else "mixed",
+                   "L": layers.L[0] if layers.n_layers == 1 else "mixed", "M": layers.M[0] if layers.n_layers == 1 else "mixed",
+                   "n_dphi": layers.n_dphi[0] if layers.n_layers == 1 else "mixed", "units_per_step": units,
+                   "precision": "fp64", "base": "black"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(layers, units)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

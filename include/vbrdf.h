@@ -1,0 +1,155 @@
+/*
+ * vbrdf — polarized subsurface BRDF of flat homogeneous particulate layers on MI355X (gfx950).
+ *
+ * Discrete-ordinate solution of the vector radiative transfer equation (Collin & Pattanaik,
+ * "GPU accelerated computation of Polarized Subsurface BRDF for Flat Particulate Layers",
+ * Sec. 2-3): the phase matrix and the radiance are split into Fourier orders (Sec. 2.B, eq. 6-15),
+ * each order is solved independently through the half-size homogeneous eigenproblem
+ * (Sec. 3.A, eq. 40-45) and the black-base boundary conditions (Sec. 3.C, eq. 49-56), for all
+ * incident Gauss-node directions at once, and the orders are summed into the BRDF Mueller matrix
+ * (Sec. 2.D, eq. 1, 12 and 39).
+ *
+ * Conventions shared by every entry point
+ *   - Layer: optical thickness tau0 > 0, single-scattering albedo 0 < omega <= 1 (clamped to
+ *     1 - 1e-12 internally), expansion coefficients coef[6][L] with rows
+ *     (alpha1, alpha2, alpha3, alpha4, beta1, beta2), l = 0..L-1, alpha1_0 = 1. The scattering
+ *     matrix is F = [[a1,b1,0,0],[b1,a2,0,0],[0,0,a3,b2],[0,0,-b2,a4]] with a1 = sum alpha1_l
+ *     d^l_00, a4 = sum alpha4_l d^l_00, a2 +- a3 = sum (alpha2 +- alpha3)_l d^l_{2,+-2},
+ *     b1 = -sum beta1_l d^l_02, b2 = -sum beta2_l d^l_02 (Wigner d-functions of cos Theta).
+ *   - Zenith grid: N-point Gauss-Legendre on [0, 1] per hemisphere (eq. 15), mu ascending.
+ *     Incident and outgoing zenith directions are these nodes.
+ *   - Azimuth grid: dphi_k = 2 pi k / n_dphi, the difference (outgoing - incident) azimuth.
+ *   - Geometry: tau grows downward, mu > 0 propagates downward; incidence (mu_q, phi0),
+ *     reflection towards (-mu_i, phi). F_r is referred to the horizontal irradiance mu_q I0.
+ *   - F_r layout per layer: [N_out = i][N_in = q][n_dphi = k][4 = r][4 = p], Stokes (I,Q,U,V).
+ *     Layers are packed back to back in the order of the plan.
+ *
+ * Memory ownership: every pointer passed to these functions stays owned by the caller. Device
+ * pointers must stay valid until the enqueued work on the given stream has completed. The plan
+ * owns its device workspace (released by vbrdf_plan_destroy).
+ *
+ * Errors: functions return a vbrdf_status. A negative value is an error; vbrdf_last_error()
+ * returns a message for the calling thread's last failed call.
+ */
+#ifndef VBRDF_H
+#define VBRDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VBRDF_ABI_VERSION 1
+
+typedef int32_t vbrdf_status;
+#define VBRDF_OK 0
+#define VBRDF_E_INVALID (-1)     /* bad pointer, shape or value */
+#define VBRDF_E_UNSUPPORTED (-2) /* valid request this library does not implement */
+#define VBRDF_E_NOMEM (-3)       /* workspace above the cap, or device allocation failed */
+#define VBRDF_E_DEVICE (-4)      /* HIP runtime error (message kept in vbrdf_last_error) */
+#define VBRDF_E_NUMERIC (-5)     /* eigen iteration did not converge, zero pivot, NaN/Inf */
+
+/* Arithmetic of the per-order solves. */
+#define VBRDF_PRECISION_FP64 0
+
+/* Plan flags. */
+#define VBRDF_FLAG_STAGE_TIMING 1 /* record a hipEvent between the stages of every solve */
+
+/* Largest supported quadrature order per hemisphere (Stokes system size 4N = 512). */
+#define VBRDF_MAX_N 128
+
+typedef struct vbrdf_plan vbrdf_plan;
+
+typedef struct vbrdf_plan_desc {
+  int32_t abi_version;       /* must equal VBRDF_ABI_VERSION */
+  int32_t n_layers;          /* >= 1 */
+  const int32_t* N;          /* host [n_layers]: nodes per hemisphere, 1..VBRDF_MAX_N */
+  const int32_t* L;          /* host [n_layers]: number of expansion coefficients, >= 1 */
+  const int32_t* M;          /* host [n_layers]: Fourier orders m = 0..M-1, 1 <= M <= L */
+  const int32_t* n_dphi;     /* host [n_layers]: azimuth samples, >= 1 */
+  int32_t precision;         /* VBRDF_PRECISION_FP64 */
+  int32_t flags;             /* 0 or VBRDF_FLAG_STAGE_TIMING */
+  uint64_t workspace_cap_bytes; /* 0 = no cap; otherwise plan creation fails with NOMEM above it */
+} vbrdf_plan_desc;
+
+/* ABI version of the loaded library (VBRDF_ABI_VERSION). */
+int32_t vbrdf_abi_version(void);
+
+/* Message for the calling thread's last failed call ("" if none). Valid until the next call
+ * into this library on the same thread. */
+const char* vbrdf_last_error(void);
+
+/* Double-Gauss nodes of eq. 15: mu[i] = (1 + x_i)/2 and alpha[i] = w_i/2 for the N-point
+ * Gauss-Legendre rule (x_i, w_i) on [-1, 1]; ascending, sum(alpha) = 1. Host only: mu and alpha
+ * are caller-owned host arrays of N doubles. Returns INVALID for N < 1 or null pointers. */
+vbrdf_status vbrdf_gauss_nodes(int32_t N, double* mu, double* alpha);
+
+/* Create a plan specialised to the layer shapes in *desc (Sec. 3: one homogeneous solution per
+ * Fourier order, shared by all incident directions). Allocates the device workspace on the
+ * current HIP device. On success *out receives the plan; on failure *out is set to NULL.
+ * Errors: INVALID (bad desc), UNSUPPORTED (N > VBRDF_MAX_N, M > 512, n_dphi > 1024, unknown
+ * precision or flags),
+ * NOMEM (cap exceeded or allocation failed), DEVICE. */
+vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* desc, vbrdf_plan** out);
+
+/* Release the plan and its workspace. Waits for nothing: the caller must make sure no enqueued
+ * solve still uses it. NULL is accepted. */
+vbrdf_status vbrdf_plan_destroy(vbrdf_plan* plan);
+
+/* Bytes of F_r the plan writes (sum over layers of N*N*n_dphi*16 doubles). */
+size_t vbrdf_plan_output_bytes(const vbrdf_plan* plan);
+
+/* Device workspace held by the plan, in bytes. */
+size_t vbrdf_plan_workspace_bytes(const vbrdf_plan* plan);
+
+/* Enqueue the BRDF of every layer on `stream` (a hipStream_t; NULL = default stream).
+ *   tau[n_layers], omega[n_layers]       device doubles
+ *   coef                                 device doubles, per layer [6][L_l] packed back to back
+ *   F_r                                  device doubles, per layer [N][N][n_dphi][4][4] packed
+ *   layer_status[n_layers]               device int32, written with VBRDF_OK or a negative code
+ * Steps per (layer, order): Legendre matrices and assembly of E and F (eq. 9-11, 41-42), the
+ * product FE (eq. 43), its eigen-decomposition (eq. 43-45), the mode vectors (eq. 45), the
+ * black-base boundary solve for all 4N incident (node, Stokes) pairs (eq. 49-56), the emergent
+ * response at tau = 0, then the Fourier synthesis of F_r (eq. 12, 39).
+ * Returns after enqueueing. Host-detectable errors (null pointers, null plan) return INVALID
+ * without enqueueing. Data-dependent problems are reported per layer in layer_status (INVALID:
+ * tau0 <= 0, omega outside (0,1], alpha1_0 != 1, non-finite input; NUMERIC: eigen iteration or
+ * boundary solve failed); such a layer's F_r is filled with NaN. */
+vbrdf_status vbrdf_solve(vbrdf_plan* plan, const double* tau, const double* omega, const double* coef,
+                         double* F_r, int32_t* layer_status, void* stream);
+
+/* Inspection of the last solve's per-order intermediates for one (layer, order), copied
+ * synchronously (after waiting for `stream`) into caller-owned host arrays:
+ *   R_out[4N*4N]   emergent response R^m[(i,r),(q,p)]: Stokes r of the upward radiance at the
+ *                  top on node i for a unit Stokes e_p entering on node q (order m), may be NULL
+ *   lam_re[4N], lam_im[4N]   eigenvalues of FE (1/nu^2), may be NULL
+ * Returns INVALID for an out-of-range layer or order. */
+vbrdf_status vbrdf_plan_inspect(const vbrdf_plan* plan, int32_t layer, int32_t m, double* R_out,
+                                double* lam_re, double* lam_im, void* stream);
+
+/* Per-stage device times (milliseconds) of the solves enqueued on a plan created with
+ * VBRDF_FLAG_STAGE_TIMING since the previous call (at most the first 256 of them), averaged per
+ * stage. hipEvents are recorded on each solve's stream between its kernel launches, so the times
+ * are those of the stream the kernels ran on. Waits for the last recorded solve, then starts a new
+ * averaging window. Writes min(cap, count) floats to ms_out (host array, may be NULL) and returns
+ * the number of stages, or a negative status (INVALID without the flag or with no recorded solve).
+ * Stage names: vbrdf_stage_name. */
+int32_t vbrdf_plan_stage_times(vbrdf_plan* plan, float* ms_out, int32_t cap);
+
+/* Name of stage i (static string), or NULL when out of range. */
+const char* vbrdf_stage_name(int32_t i);
+
+/* Stokes radiances of eq. 1 from a solved F_r: for incidence I0 (4 Stokes) on node q at azimuth
+ * phi0 = 0, I_out[i][k][r] = mu_q sum_p F_r[layer][i][q][k][r][p] I0[p], the upward radiance at
+ * the top towards (-mu_i, dphi_k). F_r and I_out are device pointers (I_out: N*n_dphi*4 doubles),
+ * I0 is a host array. Enqueued on `stream`. */
+vbrdf_status vbrdf_radiance(const vbrdf_plan* plan, const double* F_r, int32_t layer, int32_t q,
+                            const double I0[4], double* I_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VBRDF_H */

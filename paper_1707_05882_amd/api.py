@@ -1,0 +1,65 @@
+"""Convenience layer over the binding: torch tensors in, per-layer F_r tensors out.
+
+torch is used only to hold device memory and to name the stream; every arithmetic step runs in
+the HIP library.
+"""
+
+import numpy as np
+import torch
+
+from . import binding
+
+
+def pack_coefficients(coefs):
+    """Concatenate per-layer (6, L_l) coefficient arrays into the flat layout of vbrdf_solve."""
+    return np.concatenate([np.ascontiguousarray(c, dtype=np.float64).ravel() for c in coefs])
+
+
+class BRDFSolver:
+    """Plan + device buffers for a fixed list of layer shapes.
+
+    solver = BRDFSolver(N=[32], L=[64], M=[64], n_dphi=[64])
+    F = solver(tau, omega, coefs)   # list of (N, N, n_dphi, 4, 4) float64 CUDA tensors
+    """
+
+    def __init__(self, N, L, M, n_dphi, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("BRDFSolver needs a ROCm GPU")
+        self.device = torch.device(device)
+        self.plan = binding.Plan(N, L, M, n_dphi)
+        sizes = self.plan.output_sizes()
+        self.F = torch.empty(sum(sizes), dtype=torch.float64, device=self.device)
+        self.status = torch.empty(self.plan.n_layers, dtype=torch.int32, device=self.device)
+        self._views = []
+        off = 0
+        for n, p, s in zip(self.plan.N, self.plan.n_dphi, sizes):
+            self._views.append(self.F[off:off + s].view(n, n, p, 4, 4))
+            off += s
+
+    def upload(self, tau, omega, coefs):
+        dev = self.device
+        t = torch.as_tensor(np.asarray(tau, dtype=np.float64), device=dev)
+        w = torch.as_tensor(np.asarray(omega, dtype=np.float64), device=dev)
+        c = torch.as_tensor(pack_coefficients(coefs), device=dev)
+        return t, w, c
+
+    def solve_device(self, tau_d, omega_d, coef_d, stream=None):
+        """Enqueue on `stream` (default: torch's current stream) with device-resident inputs."""
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        self.plan.solve(tau_d, omega_d, coef_d, self.F, self.status, s.cuda_stream)
+
+    def check(self):
+        st = self.status.cpu().numpy()
+        bad = np.nonzero(st)[0]
+        if len(bad):
+            raise binding.VbrdfError(int(st[bad[0]]), f"layer(s) {bad.tolist()} failed with status {st[bad].tolist()}")
+
+    def __call__(self, tau, omega, coefs):
+        t, w, c = self.upload(tau, omega, coefs)
+        self.solve_device(t, w, c)
+        torch.cuda.synchronize(self.device)
+        self.check()
+        return self._views
+
+    def layer(self, i):
+        return self._views[i]

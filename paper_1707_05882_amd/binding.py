@@ -1,0 +1,198 @@
+"""ctypes binding of the C-ABI in include/vbrdf.h (argument marshalling only).
+
+Every entry point keeps the name of the C function without the ``vbrdf_`` prefix. Device buffers
+are passed as raw pointers (torch tensors are accepted and their ``data_ptr()`` is used); the
+stream is a hipStream_t handle as an integer (``torch.cuda.current_stream().cuda_stream``).
+The library is loaded from this directory; if it has not been built, loading raises instead of
+falling back to anything else.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvbrdf.so")
+
+OK = 0
+E_INVALID = -1
+E_UNSUPPORTED = -2
+E_NOMEM = -3
+E_DEVICE = -4
+E_NUMERIC = -5
+PRECISION_FP64 = 0
+FLAG_STAGE_TIMING = 1
+ABI_VERSION = 1
+MAX_N = 128
+
+STATUS_NAMES = {OK: "OK", E_INVALID: "INVALID", E_UNSUPPORTED: "UNSUPPORTED", E_NOMEM: "NOMEM",
+                E_DEVICE: "DEVICE", E_NUMERIC: "NUMERIC"}
+
+EXPORTED = (
+    "vbrdf_abi_version", "vbrdf_last_error", "vbrdf_gauss_nodes", "vbrdf_plan_create",
+    "vbrdf_plan_destroy", "vbrdf_plan_output_bytes", "vbrdf_plan_workspace_bytes", "vbrdf_solve",
+    "vbrdf_plan_inspect", "vbrdf_radiance", "vbrdf_plan_stage_times", "vbrdf_stage_name",
+)
+
+
+class VbrdfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vbrdf {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("n_layers", ctypes.c_int32),
+        ("N", ctypes.POINTER(ctypes.c_int32)),
+        ("L", ctypes.POINTER(ctypes.c_int32)),
+        ("M", ctypes.POINTER(ctypes.c_int32)),
+        ("n_dphi", ctypes.POINTER(ctypes.c_int32)),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("workspace_cap_bytes", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libvbrdf.so (raises OSError if it is missing or cannot be loaded)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is not built; build it with paper_1707_05882_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, vp, dp = ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    L.vbrdf_abi_version.restype = i32
+    L.vbrdf_abi_version.argtypes = []
+    L.vbrdf_last_error.restype = ctypes.c_char_p
+    L.vbrdf_last_error.argtypes = []
+    L.vbrdf_gauss_nodes.restype = i32
+    L.vbrdf_gauss_nodes.argtypes = [i32, dp, dp]
+    L.vbrdf_plan_create.restype = i32
+    L.vbrdf_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)]
+    L.vbrdf_plan_destroy.restype = i32
+    L.vbrdf_plan_destroy.argtypes = [vp]
+    L.vbrdf_plan_output_bytes.restype = ctypes.c_size_t
+    L.vbrdf_plan_output_bytes.argtypes = [vp]
+    L.vbrdf_plan_workspace_bytes.restype = ctypes.c_size_t
+    L.vbrdf_plan_workspace_bytes.argtypes = [vp]
+    L.vbrdf_solve.restype = i32
+    L.vbrdf_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.vbrdf_plan_inspect.restype = i32
+    L.vbrdf_plan_inspect.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.vbrdf_radiance.restype = i32
+    L.vbrdf_radiance.argtypes = [vp, vp, i32, i32, dp, vp, vp]
+    L.vbrdf_plan_stage_times.restype = i32
+    L.vbrdf_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+    L.vbrdf_stage_name.restype = ctypes.c_char_p
+    L.vbrdf_stage_name.argtypes = [i32]
+    if L.vbrdf_abi_version() != ABI_VERSION:
+        raise OSError("libvbrdf.so ABI version mismatch")
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != OK:
+        raise VbrdfError(code, load().vbrdf_last_error().decode())
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return ctypes.c_void_p(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return ctypes.c_void_p(x.ctypes.data)
+    return ctypes.c_void_p(int(x))
+
+
+def abi_version():
+    return load().vbrdf_abi_version()
+
+
+def last_error():
+    return load().vbrdf_last_error().decode()
+
+
+def gauss_nodes(N):
+    """Host call: (mu, alpha) double-Gauss nodes and weights, ascending."""
+    mu = np.zeros(max(N, 0))
+    al = np.zeros(max(N, 0))
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(load().vbrdf_gauss_nodes(int(N), mu.ctypes.data_as(dp), al.ctypes.data_as(dp)))
+    return mu, al
+
+
+class Plan:
+    """Owns a vbrdf_plan. Shapes are per-layer lists (or scalars for one layer)."""
+
+    def __init__(self, N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, workspace_cap_bytes=0):
+        as_list = lambda v: [int(x) for x in (v if hasattr(v, "__len__") else [v])]
+        self.N, self.L, self.M, self.n_dphi = (as_list(v) for v in (N, L, M, n_dphi))
+        nl = len(self.N)
+        if not (len(self.L) == len(self.M) == len(self.n_dphi) == nl):
+            raise ValueError("shape lists differ in length")
+        arr = lambda v: (ctypes.c_int32 * nl)(*v)
+        self._keep = [arr(self.N), arr(self.L), arr(self.M), arr(self.n_dphi)]
+        desc = PlanDesc(ABI_VERSION, nl, *self._keep, int(precision), int(flags), int(workspace_cap_bytes))
+        h = ctypes.c_void_p()
+        _check(load().vbrdf_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+        self.n_layers = nl
+
+    @property
+    def handle(self):
+        return self._h
+
+    def output_bytes(self):
+        return load().vbrdf_plan_output_bytes(self._h)
+
+    def workspace_bytes(self):
+        return load().vbrdf_plan_workspace_bytes(self._h)
+
+    def output_sizes(self):
+        return [n * n * p * 16 for n, p in zip(self.N, self.n_dphi)]
+
+    def solve(self, tau, omega, coef, F_r, layer_status, stream=0):
+        _check(load().vbrdf_solve(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(F_r), _ptr(layer_status),
+                                  ctypes.c_void_p(int(stream))))
+
+    def inspect(self, layer, m, stream=0):
+        """Host copies of R^m (4N x 4N) and the eigenvalues of FE for one (layer, order)."""
+        n = 4 * self.N[layer]
+        R = np.zeros((n, n))
+        lr = np.zeros(n)
+        li = np.zeros(n)
+        _check(load().vbrdf_plan_inspect(self._h, int(layer), int(m), _ptr(R), _ptr(lr), _ptr(li),
+                                         ctypes.c_void_p(int(stream))))
+        return R, lr + 1j * li
+
+    def stage_times(self):
+        """{stage name: ms} of the last solve (plan created with FLAG_STAGE_TIMING)."""
+        buf = (ctypes.c_float * 64)()
+        n = load().vbrdf_plan_stage_times(self._h, buf, 64)
+        if n < 0:
+            _check(n)
+        return {load().vbrdf_stage_name(i).decode(): float(buf[i]) for i in range(n)}
+
+    def radiance(self, F_r, layer, q, I0, I_out, stream=0):
+        i0 = (ctypes.c_double * 4)(*[float(v) for v in I0])
+        _check(load().vbrdf_radiance(self._h, _ptr(F_r), int(layer), int(q), i0, _ptr(I_out),
+                                     ctypes.c_void_p(int(stream))))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().vbrdf_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

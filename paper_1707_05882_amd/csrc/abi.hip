@@ -1,0 +1,348 @@
+// C-ABI of the library: plans, validation, launch sequence and error reporting.
+//
+// A plan is specialised to a list of layer shapes (N, L, M, n_dphi). It owns the quadrature table,
+// the work-item table (one item per (layer, Fourier order)), the synthesis task table and one
+// device workspace block per item. vbrdf_solve only enqueues kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/vbrdf.h"
+#include "vbrdf_internal.hpp"
+
+using namespace vbrdf;
+
+namespace {
+
+constexpr int kNumStages = 12;
+constexpr int kTimedSolves = 256;  // solves whose stage events are kept between queries
+const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen", "gemm_U",
+                                             "gemm_V", "colscal", "bcbuild", "rdiv", "response", "synth"};
+
+thread_local std::string g_err;
+
+vbrdf_status fail(vbrdf_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(VBRDF_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// P_N(z) and P_N'(z) by the three-term recurrence.
+void legendre_pn(int N, double z, double& pn, double& dpn) {
+  double p1 = 1.0, p0 = 0.0;
+  for (int k = 1; k <= N; ++k) {
+    const double p2 = p0;
+    p0 = p1;
+    p1 = ((2.0 * k - 1.0) * z * p0 - (k - 1.0) * p2) / k;
+  }
+  pn = p1;
+  dpn = N * (z * p1 - p0) / (z * z - 1.0);
+}
+
+// N-point Gauss-Legendre rule on [-1, 1], nodes ascending: Newton iteration on P_N from the
+// classical cosine guesses, weights w = 2 / ((1 - x^2) P_N'(x)^2).
+void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(N, 0.0);
+  w.assign(N, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < (N + 1) / 2; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (N + 0.5));
+    double pn, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre_pn(N, z, pn, dp);
+      const double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-15) break;
+    }
+    legendre_pn(N, z, pn, dp);  // one more step at the converged node
+    z -= pn / dp;
+    legendre_pn(N, z, pn, dp);
+    const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+    x[i] = -z;
+    x[N - 1 - i] = z;
+    w[i] = wi;
+    w[N - 1 - i] = wi;
+  }
+  if (N % 2 == 1) x[N / 2] = 0.0;
+}
+
+template <class T>
+vbrdf_status upload(const std::vector<T>& h, T** d) {
+  *d = nullptr;
+  if (h.empty()) return VBRDF_OK;
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(d), h.size() * sizeof(T)));
+  HIP_TRY(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return VBRDF_OK;
+}
+
+}  // namespace
+
+struct vbrdf_plan {
+  int n_layers = 0;
+  int n_items = 0;
+  int max_n = 0;
+  int max_N = 0;
+  int precision = VBRDF_PRECISION_FP64;
+  size_t out_doubles = 0;
+  size_t ws_bytes = 0;
+  std::vector<Layer> layers_h;
+  std::vector<Item> items_h;
+  Layer* layers_d = nullptr;
+  Item* items_d = nullptr;
+  SynthTask* tasks_d = nullptr;
+  int n_tasks = 0;
+  double* quad_d = nullptr;
+  double* ws_d = nullptr;
+  bool timing = false;
+  int timed = 0;  // solves recorded since the last stage_times query (capped at kTimedSolves)
+  std::vector<hipEvent_t> ev;  // kTimedSolves sets of kNumStages + 1 events
+
+  ~vbrdf_plan() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (layers_d) (void)hipFree(layers_d);
+    if (items_d) (void)hipFree(items_d);
+    if (tasks_d) (void)hipFree(tasks_d);
+    if (quad_d) (void)hipFree(quad_d);
+    if (ws_d) (void)hipFree(ws_d);
+  }
+};
+
+extern "C" {
+
+int32_t vbrdf_abi_version(void) { return VBRDF_ABI_VERSION; }
+
+const char* vbrdf_last_error(void) { return g_err.c_str(); }
+
+vbrdf_status vbrdf_gauss_nodes(int32_t N, double* mu, double* alpha) {
+  if (N < 1) return fail(VBRDF_E_INVALID, "N must be >= 1 (got %d)", N);
+  if (!mu || !alpha) return fail(VBRDF_E_INVALID, "null output pointer");
+  std::vector<double> x, w;
+  gauss_legendre(N, x, w);
+  for (int i = 0; i < N; ++i) {
+    mu[i] = 0.5 * (1.0 + x[i]);
+    alpha[i] = 0.5 * w[i];
+  }
+  return VBRDF_OK;
+}
+
+vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
+  if (!out) return fail(VBRDF_E_INVALID, "null plan output pointer");
+  *out = nullptr;
+  if (!d) return fail(VBRDF_E_INVALID, "null plan descriptor");
+  if (d->abi_version != VBRDF_ABI_VERSION)
+    return fail(VBRDF_E_INVALID, "abi_version %d does not match library %d", d->abi_version, VBRDF_ABI_VERSION);
+  if (d->n_layers < 1) return fail(VBRDF_E_INVALID, "n_layers must be >= 1");
+  if (!d->N || !d->L || !d->M || !d->n_dphi) return fail(VBRDF_E_INVALID, "null shape array");
+  if (d->precision != VBRDF_PRECISION_FP64) return fail(VBRDF_E_UNSUPPORTED, "unknown precision %d", d->precision);
+  if (d->flags & ~VBRDF_FLAG_STAGE_TIMING) return fail(VBRDF_E_UNSUPPORTED, "unknown flags 0x%x", d->flags);
+  for (int l = 0; l < d->n_layers; ++l) {
+    const int N = d->N[l], L = d->L[l], M = d->M[l], P = d->n_dphi[l];
+    if (N < 1 || L < 1 || M < 1 || P < 1) return fail(VBRDF_E_INVALID, "layer %d: N, L, M, n_dphi must be >= 1", l);
+    if (M > L) return fail(VBRDF_E_INVALID, "layer %d: M = %d exceeds L = %d", l, M, L);
+    if (N > VBRDF_MAX_N) return fail(VBRDF_E_UNSUPPORTED, "layer %d: N = %d above %d", l, N, VBRDF_MAX_N);
+    if (M > kSynthMaxM) return fail(VBRDF_E_UNSUPPORTED, "layer %d: M = %d above %d", l, M, kSynthMaxM);
+    if (P > kSynthMaxPhi) return fail(VBRDF_E_UNSUPPORTED, "layer %d: n_dphi = %d above %d", l, P, kSynthMaxPhi);
+  }
+
+  vbrdf_plan* p = new (std::nothrow) vbrdf_plan();
+  if (!p) return fail(VBRDF_E_NOMEM, "host allocation failed");
+  p->n_layers = d->n_layers;
+  std::vector<double> quad;
+  std::vector<SynthTask> tasks;
+  int64_t coef_off = 0, out_off = 0, ws_off = 0;
+  for (int l = 0; l < d->n_layers; ++l) {
+    Layer ly{};
+    ly.N = d->N[l];
+    ly.L = d->L[l];
+    ly.M = d->M[l];
+    ly.n_dphi = d->n_dphi[l];
+    ly.coef_off = coef_off;
+    ly.out_off = out_off;
+    ly.quad_off = (int64_t)quad.size();
+    ly.item0 = (int64_t)p->items_h.size();
+    std::vector<double> x, w;
+    gauss_legendre(ly.N, x, w);
+    for (int i = 0; i < ly.N; ++i) quad.push_back(0.5 * (1.0 + x[i]));
+    for (int i = 0; i < ly.N; ++i) quad.push_back(0.5 * w[i]);
+    const int n = 4 * ly.N;
+    for (int m = 0; m < ly.M; ++m) {
+      Item it{};
+      it.layer = l;
+      it.m = m;
+      it.N = ly.N;
+      it.L = ly.L;
+      it.n = n;
+      it.ws = ws_off;
+      ws_off += (item_doubles(n, ly.N, ly.L) + 31) / 32 * 32;  // 256-byte aligned blocks
+      p->items_h.push_back(it);
+    }
+    for (int i = 0; i < ly.N; ++i)
+      for (int q = 0; q < ly.N; ++q) tasks.push_back(SynthTask{l, i, q, 0});
+    p->max_n = std::max(p->max_n, n);
+    p->max_N = std::max(p->max_N, ly.N);
+    coef_off += 6 * (int64_t)ly.L;
+    out_off += (int64_t)ly.N * ly.N * ly.n_dphi * 16;
+    p->layers_h.push_back(ly);
+  }
+  p->n_items = (int)p->items_h.size();
+  p->n_tasks = (int)tasks.size();
+  p->out_doubles = (size_t)out_off;
+  p->ws_bytes = (size_t)ws_off * sizeof(double);
+  if (d->workspace_cap_bytes && p->ws_bytes > d->workspace_cap_bytes) {
+    size_t need = p->ws_bytes;
+    delete p;
+    return fail(VBRDF_E_NOMEM, "workspace %zu bytes exceeds the cap %llu", need,
+                (unsigned long long)d->workspace_cap_bytes);
+  }
+  vbrdf_status st;
+  if ((st = upload(p->layers_h, &p->layers_d)) != VBRDF_OK || (st = upload(p->items_h, &p->items_d)) != VBRDF_OK ||
+      (st = upload(tasks, &p->tasks_d)) != VBRDF_OK || (st = upload(quad, &p->quad_d)) != VBRDF_OK) {
+    delete p;
+    return st;
+  }
+  if (d->flags & VBRDF_FLAG_STAGE_TIMING) {
+    p->timing = true;
+    p->ev.assign((size_t)kTimedSolves * (kNumStages + 1), nullptr);
+    for (auto& ev : p->ev) {
+      hipError_t ee = hipEventCreate(&ev);
+      if (ee != hipSuccess) {
+        delete p;
+        return fail(VBRDF_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(ee));
+      }
+    }
+  }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->ws_d), p->ws_bytes);
+  if (e != hipSuccess) {
+    size_t need = p->ws_bytes;
+    delete p;
+    return fail(VBRDF_E_NOMEM, "workspace allocation of %zu bytes failed: %s", need, hipGetErrorString(e));
+  }
+  *out = p;
+  return VBRDF_OK;
+}
+
+vbrdf_status vbrdf_plan_destroy(vbrdf_plan* plan) {
+  delete plan;
+  return VBRDF_OK;
+}
+
+size_t vbrdf_plan_output_bytes(const vbrdf_plan* plan) { return plan ? plan->out_doubles * sizeof(double) : 0; }
+
+size_t vbrdf_plan_workspace_bytes(const vbrdf_plan* plan) { return plan ? plan->ws_bytes : 0; }
+
+vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, const double* coef, double* F_r,
+                         int32_t* layer_status, void* stream) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int ni = p->n_items, mn = p->max_n, mN = p->max_N;
+  int stage = 0;
+  const bool rec = p->timing && p->timed < kTimedSolves;
+  hipEvent_t* evs = rec ? &p->ev[(size_t)p->timed * (kNumStages + 1)] : nullptr;
+  auto mark = [&]() {
+    if (rec) (void)hipEventRecord(evs[stage], s);
+    ++stage;
+  };
+  mark();
+  k_validate<<<(p->n_layers + 63) / 64, 64, 0, s>>>(p->layers_d, p->n_layers, tau, omega, coef, layer_status);
+  mark();
+  k_legendre<<<ni, 128, 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
+  mark();
+  const int at = (mN + 15) / 16;
+  k_assemble<<<dim3(at, at, ni), 256, 0, s>>>(p->items_d, p->layers_d, p->quad_d, omega, coef, p->ws_d, layer_status);
+  mark();
+  const int gt = (mn + 63) / 64;
+  const dim3 gg(gt, gt, ni);
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, 0, kBufE, kBufG, layer_status);  // G = F~ E~
+  mark();
+  k_eigen<<<ni, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  mark();
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufU, layer_status);  // U = (D Z) X
+  mark();
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufF, layer_status);  // V = E~ U
+  mark();
+  k_colscal<<<dim3((mn + 63) / 64, ni), 64, 0, s>>>(p->items_d, tau, p->ws_d, layer_status);
+  mark();
+  const int et = (mn + 15) / 16;
+  k_bcbuild<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
+  mark();
+  k_rdiv<<<dim3(ni, 2), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  mark();
+  k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
+  mark();
+  k_synth<<<p->n_tasks, 256, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
+  mark();
+  if (rec) ++p->timed;
+  HIP_TRY(hipGetLastError());
+  return VBRDF_OK;
+}
+
+vbrdf_status vbrdf_plan_inspect(const vbrdf_plan* p, int32_t layer, int32_t m, double* R_out, double* lam_re,
+                                double* lam_im, void* stream) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (layer < 0 || layer >= p->n_layers) return fail(VBRDF_E_INVALID, "layer %d out of range", layer);
+  const Layer& ly = p->layers_h[layer];
+  if (m < 0 || m >= ly.M) return fail(VBRDF_E_INVALID, "order %d out of range", m);
+  const Item& it = p->items_h[ly.item0 + m];
+  const int n = it.n;
+  HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  const double* base = p->ws_d + it.ws;
+  if (R_out) HIP_TRY(hipMemcpy(R_out, base + (int64_t)kBufE * n * n, sizeof(double) * n * n, hipMemcpyDeviceToHost));
+  if (lam_re) HIP_TRY(hipMemcpy(lam_re, base + extras_off(n), sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (lam_im) HIP_TRY(hipMemcpy(lam_im, base + extras_off(n) + n, sizeof(double) * n, hipMemcpyDeviceToHost));
+  return VBRDF_OK;
+}
+
+int32_t vbrdf_plan_stage_times(vbrdf_plan* p, float* ms_out, int32_t cap) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!p->timing || p->timed == 0) return fail(VBRDF_E_INVALID, "plan has no timed solve");
+  const int nsolve = p->timed;
+  HIP_TRY(hipEventSynchronize(p->ev[(size_t)(nsolve - 1) * (kNumStages + 1) + kNumStages]));
+  for (int i = 0; i < kNumStages && i < cap; ++i) {
+    double sum = 0.0;
+    for (int k = 0; k < nsolve; ++k) {
+      float ms = 0.0f;
+      const hipEvent_t* e = &p->ev[(size_t)k * (kNumStages + 1)];
+      HIP_TRY(hipEventElapsedTime(&ms, e[i], e[i + 1]));
+      sum += ms;
+    }
+    if (ms_out) ms_out[i] = (float)(sum / nsolve);
+  }
+  p->timed = 0;
+  return kNumStages;
+}
+
+const char* vbrdf_stage_name(int32_t i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : nullptr; }
+
+vbrdf_status vbrdf_radiance(const vbrdf_plan* p, const double* F_r, int32_t layer, int32_t q, const double I0[4],
+                            double* I_out, void* stream) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!F_r || !I0 || !I_out) return fail(VBRDF_E_INVALID, "null pointer");
+  if (layer < 0 || layer >= p->n_layers) return fail(VBRDF_E_INVALID, "layer %d out of range", layer);
+  const Layer& ly = p->layers_h[layer];
+  if (q < 0 || q >= ly.N) return fail(VBRDF_E_INVALID, "incident node %d out of range", q);
+  const int total = ly.N * ly.n_dphi * 4;
+  k_radiance<<<(total + 255) / 256, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(
+      p->layers_d, layer, q, p->quad_d, F_r, I0[0], I0[1], I0[2], I0[3], I_out);
+  HIP_TRY(hipGetLastError());
+  return VBRDF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+// Input validation, Legendre matrices and assembly of the half-size matrices E~ and F~.
+//
+// Per Fourier order m the phase-matrix coefficient A^m(mu, mu') is the sum over degrees l of
+// P_l^m(mu) B_l P_l^m(mu') (Sec. 2.B, eq. 9), with the Legendre matrices
+// P_l^m = [[Pb,0,0,0],[0,R,-T,0],[0,-T,R,0],[0,0,0,Pb]] (eq. 9-11) built from Wigner d-functions:
+// Pb = d^l_{m0}, R = -(d^l_{m2} + d^l_{m,-2})/2, T = -(d^l_{m2} - d^l_{m,-2})/2. The half-size
+// reduction (Sec. 3.A, eq. 41) needs S+- = sum_l Pi_l B_l [I4 +- (-1)^(l-m) D] Pi_l^T on the
+// Gauss nodes. Since B_l (I4 + D) keeps the IQ columns of B_l and B_l (I4 - D) the UV columns,
+// each 4x4 block of S+- is a sum of an "IQ part" and a "UV part" over the two parity classes of
+// l - m. The kernel forms E~ = M^-1 (I - omega/2 S+ W) and F~ = M^-1 (I - omega/2 S- W), which
+// are similar to the paper's E and F (E = M E~ M^-1) and have the same spectrum products.
+#include "vbrdf_internal.hpp"
+
+namespace vbrdf {
+
+__global__ void k_validate(const Layer* layers, int n_layers, const double* tau, const double* omega,
+                           const double* coef, int32_t* status) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_layers) return;
+  const Layer ly = layers[l];
+  int32_t st = 0;
+  double t = tau[l], w = omega[l];
+  if (!(t > 0.0) || !isfinite(t)) st = -1;
+  if (!(w > 0.0) || !(w <= 1.0)) st = -1;
+  const double* c = coef + ly.coef_off;
+  if (!(fabs(c[0] - 1.0) <= 1e-12)) st = -1;
+  for (int k = 0; k < 6 * ly.L; ++k)
+    if (!isfinite(c[k])) st = -1;
+  status[l] = st;
+}
+
+// Start value of d^l_{mn}(x) at l = lmin = max(|m|, |n|), computed in logarithms so that large
+// orders neither overflow the prefactor nor lose the small power of (1 - x^2).
+__device__ inline double wigner_start(int m, int n, double x, int lmin) {
+  int amn = abs(m - n), apn = abs(m + n);
+  double lg = 0.5 * (lgamma(2.0 * lmin + 1.0) - lgamma(amn + 1.0) - lgamma(apn + 1.0)) - lmin * 0.6931471805599453;
+  if (amn) lg += 0.5 * amn * log1p(-x);
+  if (apn) lg += 0.5 * apn * log1p(x);
+  double v = exp(lg);
+  if (n < m && ((m - n) & 1)) v = -v;
+  return v;
+}
+
+// One upward step of the three-term recurrence of d^s_{mn} in s: returns d^{s+1}.
+__device__ inline double wigner_step(int s, int m, int n, double x, double d_s, double d_sm1) {
+  double a = (2.0 * s + 1.0) * (s * (s + 1.0) * x - (double)m * n);
+  double b = (s + 1.0) * sqrt(((double)s * s - (double)m * m) * ((double)s * s - (double)n * n));
+  double c = s * sqrt(((s + 1.0) * (s + 1.0) - (double)m * m) * ((s + 1.0) * (s + 1.0) - (double)n * n));
+  return (a * d_s - b * d_sm1) / c;
+}
+
+struct WSeq {
+  int m, n, lmin;
+  double prev, cur;  // d^{l-1}, d^l at the current l
+};
+
+__device__ inline double wseq_value(WSeq& q, int l, double x) {
+  // returns d^l_{mn}(x) for increasing l = 0, 1, 2, ... (called once per l in order)
+  if (l < q.lmin) return 0.0;
+  if (l == q.lmin) {
+    q.prev = 0.0;
+    q.cur = wigner_start(q.m, q.n, x, q.lmin);
+    return q.cur;
+  }
+  double nxt;
+  if (l - 1 == 0)
+    nxt = x * q.cur;  // m = n = 0: d^1_00 = x
+  else
+    nxt = wigner_step(l - 1, q.m, q.n, x, q.cur, q.prev);
+  q.prev = q.cur;
+  q.cur = nxt;
+  return nxt;
+}
+
+// Legendre table per item: leg[(l * N + i) * 3 + {0,1,2}] = (Pb, R, T) of order m at mu_i.
+__global__ void k_legendre(const Item* items, const Layer* layers, const double* quad, double* ws,
+                           const int32_t* status) {
+  const Item it = items[blockIdx.x];
+  if (status[it.layer] != 0) return;
+  const Layer ly = layers[it.layer];
+  const int N = it.N, L = it.L, m = it.m;
+  double* leg = ws + it.ws + leg_off(it.n);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const double x = quad[ly.quad_off + i];
+    WSeq s0{m, 0, m, 0.0, 0.0};
+    WSeq sp{m, 2, m > 2 ? m : 2, 0.0, 0.0};
+    WSeq sm{m, -2, m > 2 ? m : 2, 0.0, 0.0};
+    for (int l = 0; l < L; ++l) {
+      double pb = wseq_value(s0, l, x);
+      double dp = wseq_value(sp, l, x);
+      double dm = wseq_value(sm, l, x);
+      double* o = leg + ((int64_t)l * N + i) * 3;
+      if (l < m) {
+        o[0] = 0.0; o[1] = 0.0; o[2] = 0.0;
+      } else {
+        o[0] = pb;
+        o[1] = -0.5 * (dp + dm);
+        o[2] = -0.5 * (dp - dm);
+      }
+    }
+  }
+}
+
+constexpr int kAsmTile = 16;   // 16 x 16 node pairs (4x4 Stokes blocks) per workgroup
+constexpr int kAsmChunk = 32;  // degrees staged per LDS pass
+
+// One workgroup per (item, tile of output node i, tile of input node j); one thread per (i, j)
+// Stokes block. Legendre values and coefficients of a chunk of degrees are staged in LDS and
+// shared by the 256 blocks of the tile.
+__global__ __launch_bounds__(256) void k_assemble(const Item* items, const Layer* layers, const double* quad,
+                                                   const double* omega, const double* coef, double* ws,
+                                                   const int32_t* status) {
+  const Item it = items[blockIdx.z];
+  if (status[it.layer] != 0) return;
+  const int N = it.N, L = it.L, m = it.m, n = it.n;
+  const int i0 = blockIdx.y * kAsmTile, j0 = blockIdx.x * kAsmTile;
+  if (i0 >= N || j0 >= N) return;
+  const Layer ly = layers[it.layer];
+  const double* leg = ws + it.ws + leg_off(n);
+  const double* cf = coef + ly.coef_off;
+
+  __shared__ double sPi[kAsmChunk][kAsmTile][3];
+  __shared__ double sPj[kAsmChunk][kAsmTile][3];
+  __shared__ double sC[6][kAsmChunk];
+
+  const int tid = threadIdx.x;
+  const int ti = tid / kAsmTile, tj = tid % kAsmTile;
+  const int i = i0 + ti, j = j0 + tj;
+
+  // accumulators: [parity][9] for the IQ part and the UV part
+  double q[2][9], u[2][9];
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { q[e][k] = 0.0; u[e][k] = 0.0; }
+
+  for (int lc = m; lc < L; lc += kAsmChunk) {
+    const int cnt = min(kAsmChunk, L - lc);
+    __syncthreads();
+    for (int t = tid; t < cnt * kAsmTile * 3; t += blockDim.x) {
+      int l = t / (kAsmTile * 3), r = t % (kAsmTile * 3);
+      int a = r / 3, c = r % 3;
+      sPi[l][a][c] = (i0 + a < N) ? leg[((int64_t)(lc + l) * N + i0 + a) * 3 + c] : 0.0;
+      sPj[l][a][c] = (j0 + a < N) ? leg[((int64_t)(lc + l) * N + j0 + a) * 3 + c] : 0.0;
+    }
+    for (int t = tid; t < 6 * cnt; t += blockDim.x) {
+      int row = t / cnt, l = t % cnt;
+      sC[row][l] = cf[(int64_t)row * L + lc + l];
+    }
+    __syncthreads();
+    for (int l = 0; l < cnt; ++l) {
+      const int e = (lc + l - m) & 1;
+      const double pi_ = sPi[l][ti][0], ri = sPi[l][ti][1], tI = sPi[l][ti][2];
+      const double pj = sPj[l][tj][0], rj = sPj[l][tj][1], tJ = sPj[l][tj][2];
+      const double a1 = sC[0][l], a2 = sC[1][l], a3 = sC[2][l], a4 = sC[3][l];
+      const double b1 = sC[4][l], b2 = sC[5][l];
+      // IQ part: Pi B_l diag(1,1,0,0) Pj
+      q[e][0] += pi_ * a1 * pj;
+      q[e][1] += pi_ * b1 * rj;
+      q[e][2] += pi_ * b1 * tJ;
+      q[e][3] += ri * b1 * pj;
+      q[e][4] += ri * a2 * rj;
+      q[e][5] += ri * a2 * tJ;
+      q[e][6] += tI * b1 * pj;
+      q[e][7] += tI * a2 * rj;
+      q[e][8] += tI * a2 * tJ;
+      // UV part: Pi B_l diag(0,0,1,1) Pj
+      u[e][0] += tI * a3 * tJ;
+      u[e][1] += tI * a3 * rj;
+      u[e][2] += tI * b2 * pj;
+      u[e][3] += ri * a3 * tJ;
+      u[e][4] += ri * a3 * rj;
+      u[e][5] += ri * b2 * pj;
+      u[e][6] += pi_ * b2 * tJ;
+      u[e][7] += pi_ * b2 * rj;
+      u[e][8] += pi_ * a4 * pj;
+    }
+  }
+  if (i >= N || j >= N) return;
+
+  // Block matrices (4x4, row r, column c) of the two parts for parity e.
+  auto iq = [&](int e, int r, int c) -> double {
+    if (r == 3 || c == 3) return 0.0;
+    const double* Q = q[e];
+    const double v[3][3] = {{Q[0], Q[1], -Q[2]}, {Q[3], Q[4], -Q[5]}, {-Q[6], -Q[7], Q[8]}};
+    return v[r][c];
+  };
+  auto uv = [&](int e, int r, int c) -> double {
+    if (r == 0 || c == 0) return 0.0;
+    const double* U = u[e];
+    const double v[3][3] = {{U[0], -U[1], -U[2]}, {-U[3], U[4], U[5]}, {U[6], -U[7], U[8]}};
+    return v[r - 1][c - 1];
+  };
+
+  const double w = fmin(omega[it.layer], kOmegaMax);
+  const double mui = quad[ly.quad_off + i];
+  const double alj = quad[ly.quad_off + N + j];
+  double* E = ws + it.ws + (int64_t)kBufE * n * n;
+  double* F = ws + it.ws + (int64_t)kBufF * n * n;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      // S+ = 2 (IQ_even + UV_odd), S- = 2 (UV_even + IQ_odd)
+      const double sp = 2.0 * (iq(0, r, c) + uv(1, r, c));
+      const double sm = 2.0 * (uv(0, r, c) + iq(1, r, c));
+      const double dl = (i == j && r == c) ? 1.0 : 0.0;
+      const int64_t idx = (int64_t)(4 * i + r) * n + 4 * j + c;
+      E[idx] = (dl - 0.5 * w * sp * alj) / mui;
+      F[idx] = (dl - 0.5 * w * sm * alj) / mui;
+    }
+  }
+}
+
+}  // namespace vbrdf

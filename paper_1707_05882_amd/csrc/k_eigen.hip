@@ -1,0 +1,529 @@
+// Batched real non-symmetric eigensolver for the homogeneous step (Sec. 3.A, eq. 43-45).
+//
+// The half-size problem (F E) X = lambda X has real or complex-conjugate eigenvalues (the vector
+// equation may produce complex pairs). The paper calls a library eigensolver once per order; here
+// one workgroup solves one (layer, order) matrix and all orders of all layers run in one launch.
+//
+// Steps (all in FP64):
+//   1. diagonal balancing by powers of two (exact similarity; the matrix is graded by 1/mu^2),
+//   2. Householder reduction to upper Hessenberg form, accumulating the orthogonal factor Z,
+//   3. implicit double-shift (Francis) QR to real Schur form T = Z^T H Z with deflation by the
+//      Ahues-Tisseur criterion, exceptional shifts every 10 stagnant sweeps, a real shift pair
+//      replaced by the eigenvalue closer to the corner used twice, and after 40 stagnant sweeps
+//      (a cluster of nearly equal eigenvalues) a normwise deflation |h| <= ulp ||H||_F,
+//   4. eigenvectors of the quasi-triangular T by back-substitution (complex arithmetic only for
+//      complex pairs), normalised, and Z scaled by the balancing factors.
+// The caller then forms U = (D Z) X_T with a GEMM. Output convention: for a complex pair stored at
+// (j, j+1) with Im lambda_j > 0, U[:, j] + i U[:, j+1] is the eigenvector of lambda_j.
+//
+// H is kept in LDS (row stride n + 1) when n <= 128 and reduced in place in global memory
+// otherwise. During a QR sweep the reflectors are kept in LDS and applied to Z afterwards, each
+// thread streaming along its own rows of Z with a three-element window.
+#include "vbrdf_internal.hpp"
+
+namespace vbrdf {
+
+constexpr double kUlp = 2.220446049250313e-16;
+constexpr double kSafeMin = 2.2250738585072014e-308;
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1)
+    if (o < (int)blockDim.x) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1)
+    if (o < (int)blockDim.x) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double block_sum(double v, double* sred) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int w = 0; w < nw; ++w) r += sred[w];
+  __syncthreads();
+  return r;
+}
+__device__ inline int block_max(int v, int* sred) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int r = sred[0];
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int w = 1; w < nw; ++w) r = max(r, sred[w]);
+  __syncthreads();
+  return r;
+}
+
+struct Cx {
+  double re, im;
+};
+__device__ inline Cx cmul(Cx a, Cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline Cx csub(Cx a, Cx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline double cabs1(Cx a) { return fabs(a.re) + fabs(a.im); }
+__device__ inline Cx cdiv(Cx a, Cx b) {
+  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, d = b.re + b.im * r;
+    return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  }
+  double r = b.re / b.im, d = b.im + b.re * r;
+  return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+__device__ inline Cx cguard(Cx d, double smin) {
+  if (cabs1(d) < smin) return {smin, 0.0};
+  return d;
+}
+
+// Solve the 2x2 complex system [[a, b], [c, d]] x = r by Gaussian elimination with pivoting;
+// tiny pivots are replaced by smin (perturbation in the style of LAPACK's eigenvector solver).
+__device__ inline void csolve2(Cx a, Cx b, Cx c, Cx d, Cx r0, Cx r1, double smin, Cx& x0, Cx& x1) {
+  if (cabs1(a) >= cabs1(c)) {
+    a = cguard(a, smin);
+    Cx f = cdiv(c, a);
+    Cx d2 = cguard(csub(d, cmul(f, b)), smin);
+    Cx s1 = csub(r1, cmul(f, r0));
+    x1 = cdiv(s1, d2);
+    x0 = cdiv(csub(r0, cmul(b, x1)), a);
+  } else {
+    Cx f = cdiv(a, c);
+    Cx b2 = cguard(csub(b, cmul(f, d)), smin);
+    Cx s0 = csub(r0, cmul(f, r1));
+    x1 = cdiv(s0, b2);
+    x0 = cdiv(csub(r1, cmul(d, x1)), c);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, int32_t* status) {
+  const Item it = items[blockIdx.x];
+  if (status[it.layer] != 0) return;
+  const int n = it.n;
+  double* base = ws + it.ws;
+  double* G = base + (int64_t)kBufG * n * n;
+  double* ZT = base + (int64_t)kBufZ * n * n;  // Z(r, c) = ZT[c * n + r]
+  double* XT = base + (int64_t)kBufX * n * n;  // eigenvector j, component i at XT[i * n + j]
+  double* ex = base + extras_off(n);
+  double* lre = ex;
+  double* lim = ex + n;
+  double* bal = ex + 2 * n;
+  int* blk = reinterpret_cast<int*>(ex + 3 * n);
+
+  __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1)];
+  __shared__ double sv[kMaxn];
+  __shared__ double srefl[3 * kMaxn];
+  __shared__ double sred[8];
+  __shared__ int sredi[8];
+  __shared__ int sctl[8];
+  __shared__ double sxyz[3];
+
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const bool in_lds = n <= kLdsMaxn;
+  double* H = in_lds ? sH : G;
+  const int64_t ld = in_lds ? n + 1 : n;
+#define HH(r, c) H[(int64_t)(r) * ld + (c)]
+#define ZZ(r, c) ZT[(int64_t)(c) * n + (r)]
+
+  // ---- load, Z = I, balance factors = 1
+  if (in_lds)
+    for (int t = tid; t < n * n; t += NT) HH(t / n, t % n) = G[t];
+  for (int t = tid; t < n * n; t += NT) ZT[t] = ((t / n) == (t % n)) ? 1.0 : 0.0;
+  for (int i = tid; i < n; i += NT) bal[i] = 1.0;
+  __syncthreads();
+
+  // ---- 1. balancing (simultaneous power-of-two row/column scalings until no gain)
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) sctl[0] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) {
+      double c = 0.0, r = 0.0;
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        c += fabs(HH(j, i));
+        r += fabs(HH(i, j));
+      }
+      double f = 1.0;
+      if (c > 0.0 && r > 0.0) {
+        int e = (int)rint(0.5 * log2(r / c));
+        e = max(-20, min(20, e));
+        if (e != 0) {
+          double ff = ldexp(1.0, e);
+          if (c * ff + r / ff < 0.95 * (c + r)) {
+            f = ff;
+            sctl[0] = 1;
+          }
+        }
+      }
+      sv[i] = f;
+    }
+    __syncthreads();
+    if (sctl[0] == 0) break;
+    for (int t = tid; t < n * n; t += NT) {
+      int r = t / n, c = t % n;
+      HH(r, c) *= sv[c] / sv[r];
+    }
+    for (int i = tid; i < n; i += NT) bal[i] *= sv[i];
+    __syncthreads();
+  }
+
+  // Frobenius norm (invariant under the orthogonal similarities that follow): backstop scale
+  // for deflation in clusters of nearly equal eigenvalues where the local test cannot be met.
+  {
+    double part = 0.0;
+    for (int t = tid; t < n * n; t += NT) {
+      const double v = HH(t / n, t % n);
+      part += v * v;
+    }
+    const double nrm2 = block_sum(part, sred);
+    if (tid == 0) sxyz[0] = sqrt(nrm2);
+    __syncthreads();
+  }
+  const double hnorm = sxyz[0];
+  __syncthreads();
+
+  // ---- 2. Householder reduction to Hessenberg form, Z accumulated
+  for (int k = 0; k + 2 < n; ++k) {
+    double part = 0.0;
+    for (int i = k + 2 + tid; i < n; i += NT) part += HH(i, k) * HH(i, k);
+    const double sigma = block_sum(part, sred);
+    if (sigma == 0.0) continue;  // column already reduced (uniform decision)
+    const double x0 = HH(k + 1, k);
+    const double nrm = sqrt(x0 * x0 + sigma);
+    const double beta = (x0 >= 0.0) ? -nrm : nrm;
+    const double tau = (beta - x0) / beta;
+    const double scal = 1.0 / (x0 - beta);
+    const int len = n - k - 1;
+    for (int i = tid; i < len; i += NT) sv[i] = (i == 0) ? 1.0 : HH(k + 1 + i, k) * scal;
+    __syncthreads();
+    for (int i = tid; i < len; i += NT) HH(k + 1 + i, k) = (i == 0) ? beta : 0.0;
+    for (int c = k + 1 + tid; c < n; c += NT) {  // left: (I - tau v v^T) H
+      double w = 0.0;
+      for (int i = 0; i < len; ++i) w += sv[i] * HH(k + 1 + i, c);
+      w *= tau;
+      for (int i = 0; i < len; ++i) HH(k + 1 + i, c) -= sv[i] * w;
+    }
+    __syncthreads();
+    for (int r = tid; r < n; r += NT) {  // right: H (I - tau v v^T), and Z likewise
+      double y = 0.0;
+      for (int i = 0; i < len; ++i) y += HH(r, k + 1 + i) * sv[i];
+      y *= tau;
+      for (int i = 0; i < len; ++i) HH(r, k + 1 + i) -= y * sv[i];
+      double yz = 0.0;
+      for (int i = 0; i < len; ++i) yz += ZZ(r, k + 1 + i) * sv[i];
+      yz *= tau;
+      for (int i = 0; i < len; ++i) ZZ(r, k + 1 + i) -= yz * sv[i];
+    }
+    __syncthreads();
+  }
+
+  // ---- 3. Francis double-shift QR to real Schur form
+  if (tid == 0) {
+    sctl[1] = n - 1;  // active bottom index hh
+    sctl[2] = 0;      // iterations since last deflation
+    sctl[3] = 0;      // total iterations
+    sctl[5] = 0;      // failure flag
+  }
+  __syncthreads();
+  while (true) {
+    const int hh = sctl[1];
+    if (hh < 0) break;
+    // parallel deflation scan: largest k in [1, hh] with a negligible subdiagonal
+    int cand = 0;
+    const bool stalled = sctl[2] >= 40;
+    for (int k = 1 + tid; k <= hh; k += NT) {
+      const double hk = fabs(HH(k, k - 1));
+      bool small = hk <= kSafeMin || (stalled && hk <= kUlp * hnorm);
+      if (!small) {
+        double tst = fabs(HH(k - 1, k - 1)) + fabs(HH(k, k));
+        if (tst == 0.0) {
+          if (k >= 2) tst += fabs(HH(k - 1, k - 2));
+          if (k + 1 <= hh) tst += fabs(HH(k + 1, k));
+        }
+        if (hk <= kUlp * tst) {
+          const double hu = fabs(HH(k - 1, k));
+          const double ab = fmax(hk, hu), ba = fmin(hk, hu);
+          const double dd = fabs(HH(k - 1, k - 1) - HH(k, k));
+          const double aa = fmax(fabs(HH(k, k)), dd), bb = fmin(fabs(HH(k, k)), dd);
+          const double s = aa + ab;
+          small = ba * (ab / s) <= fmax(kSafeMin, kUlp * (bb * (aa / s)));
+        }
+      }
+      if (small) cand = max(cand, k);
+    }
+    const int l = block_max(cand, sredi);
+    if (tid == 0) {
+      if (l > 0) HH(l, l - 1) = 0.0;
+      if (l == hh) {  // 1x1 block
+        lre[hh] = HH(hh, hh);
+        lim[hh] = 0.0;
+        blk[hh] = 1;
+        sctl[1] = hh - 1;
+        sctl[2] = 0;
+        sctl[4] = 0;
+      } else if (l == hh - 1) {  // 2x2 block
+        const double a = HH(hh - 1, hh - 1), b = HH(hh - 1, hh), c = HH(hh, hh - 1), d = HH(hh, hh);
+        const double p = 0.5 * (a - d), bc = b * c, disc = p * p + bc;
+        if (disc >= 0.0) {
+          const double zz = p + copysign(sqrt(disc), p);
+          lre[hh - 1] = d + zz;
+          lre[hh] = (zz != 0.0) ? d - bc / zz : d;
+          lim[hh - 1] = 0.0;
+          lim[hh] = 0.0;
+        } else {
+          lre[hh - 1] = lre[hh] = 0.5 * (a + d);
+          lim[hh - 1] = sqrt(-disc);
+          lim[hh] = -sqrt(-disc);
+        }
+        blk[hh - 1] = 2;
+        blk[hh] = 0;
+        sctl[1] = hh - 2;
+        sctl[2] = 0;
+        sctl[4] = 0;
+      } else {
+        const int its = ++sctl[2];
+        const int tot = ++sctl[3];
+        if (its > 100 || tot > 60 * n) {
+          sctl[5] = 1;
+          sctl[4] = 0;
+          sctl[1] = -1;
+        } else {
+          double h11, h12, h21, h22;
+          if (its % 20 == 10) {
+            const double s = fabs(HH(l + 1, l)) + fabs(HH(l + 2, l + 1));
+            h11 = 0.75 * s + HH(l, l);
+            h12 = -0.4375 * s;
+            h21 = s;
+            h22 = h11;
+          } else if (its % 20 == 0) {
+            const double s = fabs(HH(hh, hh - 1)) + fabs(HH(hh - 1, hh - 2));
+            h11 = 0.75 * s + HH(hh, hh);
+            h12 = -0.4375 * s;
+            h21 = s;
+            h22 = h11;
+          } else {
+            h11 = HH(hh - 1, hh - 1);
+            h12 = HH(hh - 1, hh);
+            h21 = HH(hh, hh - 1);
+            h22 = HH(hh, hh);
+          }
+          // shifts = eigenvalues of [[h11, h12], [h21, h22]]; a real pair is replaced by the root
+          // closer to h22 used twice (keeps the iteration from stagnating on real clusters)
+          double s1r, s1i, s2r, s2i;
+          {
+            const double hp = 0.5 * (h11 - h22), bc = h12 * h21, disc = hp * hp + bc;
+            if (disc >= 0.0) {
+              const double zz = hp + copysign(sqrt(disc), hp);
+              const double d1 = zz, d2 = (zz != 0.0) ? -bc / zz : 0.0;  // root - h22
+              const double rt = h22 + ((fabs(d1) <= fabs(d2)) ? d1 : d2);
+              s1r = s2r = rt;
+              s1i = s2i = 0.0;
+            } else {
+              s1r = s2r = h22 + hp;
+              s1i = sqrt(-disc);
+              s2i = -s1i;
+            }
+          }
+          // first column of (H - s1)(H - s2) at row l, in product form (no cancellation)
+          const double a0 = HH(l, l), a1 = HH(l + 1, l);
+          const double sc = fabs(a0 - s2r) + fabs(s2i) + fabs(a1);
+          const double a1s = a1 / sc;
+          sxyz[0] = a1s * HH(l, l + 1) + (a0 - s1r) * ((a0 - s2r) / sc) - s1i * (s2i / sc);
+          sxyz[1] = a1s * (a0 + HH(l + 1, l + 1) - s1r - s2r);
+          sxyz[2] = a1s * HH(l + 2, l + 1);
+          sctl[6] = l;
+          sctl[4] = 1;  // sweep
+        }
+      }
+    }
+    __syncthreads();
+    if (sctl[4] == 0) continue;  // deflated (or failed: hh < 0 ends the loop)
+
+    const int lo = sctl[6];
+    for (int k = lo; k <= hh - 1; ++k) {
+      const bool three = k < hh - 1;
+      if (tid == 0) {
+        double x, y, z;
+        if (k == lo) {
+          x = sxyz[0];
+          y = sxyz[1];
+          z = sxyz[2];
+        } else {
+          x = HH(k, k - 1);
+          y = HH(k + 1, k - 1);
+          z = three ? HH(k + 2, k - 1) : 0.0;
+        }
+        if (!three) z = 0.0;
+        const double nrm = sqrt(x * x + y * y + z * z);
+        double tau = 0.0, u1 = 0.0, u2 = 0.0;
+        if (nrm != 0.0 && (y != 0.0 || z != 0.0)) {
+          const double beta = (x >= 0.0) ? -nrm : nrm;
+          tau = (beta - x) / beta;
+          const double sc = 1.0 / (x - beta);
+          u1 = y * sc;
+          u2 = z * sc;
+          if (k > lo) {
+            HH(k, k - 1) = beta;
+            HH(k + 1, k - 1) = 0.0;
+            if (three) HH(k + 2, k - 1) = 0.0;
+          }
+        }
+        srefl[3 * k] = tau;
+        srefl[3 * k + 1] = u1;
+        srefl[3 * k + 2] = u2;
+      }
+      __syncthreads();
+      const double tau = srefl[3 * k], u1 = srefl[3 * k + 1], u2 = srefl[3 * k + 2];
+      if (tau != 0.0) {
+        for (int c = k + tid; c < n; c += NT) {  // rows k..k+2, all columns right of k-1
+          if (three) {
+            const double w = tau * (HH(k, c) + u1 * HH(k + 1, c) + u2 * HH(k + 2, c));
+            HH(k, c) -= w;
+            HH(k + 1, c) -= w * u1;
+            HH(k + 2, c) -= w * u2;
+          } else {
+            const double w = tau * (HH(k, c) + u1 * HH(k + 1, c));
+            HH(k, c) -= w;
+            HH(k + 1, c) -= w * u1;
+          }
+        }
+        __syncthreads();
+        const int rmax = min(k + 3, hh);
+        for (int r = tid; r <= rmax; r += NT) {  // columns k..k+2, rows 0..k+3
+          if (three) {
+            const double w = tau * (HH(r, k) + u1 * HH(r, k + 1) + u2 * HH(r, k + 2));
+            HH(r, k) -= w;
+            HH(r, k + 1) -= w * u1;
+            HH(r, k + 2) -= w * u2;
+          } else {
+            const double w = tau * (HH(r, k) + u1 * HH(r, k + 1));
+            HH(r, k) -= w;
+            HH(r, k + 1) -= w * u1;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // delayed application of the sweep's reflectors to the rows of Z
+    for (int r = tid; r < n; r += NT) {
+      double z0 = ZZ(r, lo), z1 = ZZ(r, lo + 1);
+      for (int k = lo; k <= hh - 1; ++k) {
+        const bool three = k < hh - 1;
+        double z2 = three ? ZZ(r, k + 2) : 0.0;
+        const double tau = srefl[3 * k];
+        if (tau != 0.0) {
+          const double u1 = srefl[3 * k + 1], u2 = srefl[3 * k + 2];
+          const double w = tau * (z0 + u1 * z1 + (three ? u2 * z2 : 0.0));
+          z0 -= w;
+          z1 -= w * u1;
+          if (three) z2 -= w * u2;
+        }
+        ZZ(r, k) = z0;
+        z0 = z1;
+        z1 = z2;
+      }
+      ZZ(r, hh) = z0;
+    }
+    __syncthreads();
+  }
+  if (sctl[5]) {
+    if (tid == 0) status[it.layer] = -5;
+    return;
+  }
+
+  // ---- 4. eigenvectors of the quasi-triangular factor by back-substitution
+  for (int j = tid; j < n; j += NT) {
+    const double wr = lre[j], wi = lim[j];
+    if (wi < 0.0) continue;  // second member of a complex pair: written by j - 1
+    const int b0 = (blk[j] == 0) ? j - 1 : j;   // own block start
+    const int bend = (blk[b0] == 2) ? b0 + 1 : b0;
+    const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
+    const bool cplx = wi > 0.0;
+    const Cx lam{wr, wi};
+    for (int i = bend + 1; i < n; ++i) {
+      XT[(int64_t)i * n + j] = 0.0;
+      if (cplx) XT[(int64_t)i * n + j + 1] = 0.0;
+    }
+    // own block
+    Cx xb0{0.0, 0.0}, xb1{0.0, 0.0};
+    if (bend == b0) {
+      xb0 = {1.0, 0.0};
+    } else {
+      const Cx a{HH(b0, b0), 0.0}, bb{HH(b0, b0 + 1), 0.0}, c{HH(b0 + 1, b0), 0.0}, d{HH(b0 + 1, b0 + 1), 0.0};
+      const Cx v0a = bb, v1a = csub(lam, a);   // (b, lambda - a)
+      const Cx v0b = csub(lam, d), v1b = c;    // (lambda - d, c)
+      if (cabs1(v0a) + cabs1(v1a) >= cabs1(v0b) + cabs1(v1b)) {
+        xb0 = v0a;
+        xb1 = v1a;
+      } else {
+        xb0 = v0b;
+        xb1 = v1b;
+      }
+      if (cabs1(xb0) + cabs1(xb1) == 0.0) {
+        if (j == b0) xb0 = {1.0, 0.0}; else xb1 = {1.0, 0.0};
+      }
+    }
+    XT[(int64_t)b0 * n + j] = xb0.re;
+    if (cplx) XT[(int64_t)b0 * n + j + 1] = xb0.im;
+    if (bend > b0) {
+      XT[(int64_t)bend * n + j] = xb1.re;
+      if (cplx) XT[(int64_t)bend * n + j + 1] = xb1.im;
+    }
+    // blocks above, bottom to top
+    int i = b0 - 1;
+    while (i >= 0) {
+      const int s = (blk[i] == 0) ? i - 1 : i;  // block [s, i]
+      Cx r0{0.0, 0.0}, r1{0.0, 0.0};
+      for (int c = i + 1; c <= bend; ++c) {
+        const Cx xc{XT[(int64_t)c * n + j], cplx ? XT[(int64_t)c * n + j + 1] : 0.0};
+        const double t0 = HH(s, c);
+        r0.re -= t0 * xc.re;
+        r0.im -= t0 * xc.im;
+        if (s < i) {
+          const double t1 = HH(i, c);
+          r1.re -= t1 * xc.re;
+          r1.im -= t1 * xc.im;
+        }
+      }
+      if (s == i) {
+        const Cx dd = cguard(csub(Cx{HH(i, i), 0.0}, lam), smin);
+        const Cx xi = cdiv(r0, dd);
+        XT[(int64_t)i * n + j] = xi.re;
+        if (cplx) XT[(int64_t)i * n + j + 1] = xi.im;
+      } else {
+        Cx x0, x1;
+        csolve2(csub(Cx{HH(s, s), 0.0}, lam), Cx{HH(s, i), 0.0}, Cx{HH(i, s), 0.0},
+                csub(Cx{HH(i, i), 0.0}, lam), r0, r1, smin, x0, x1);
+        XT[(int64_t)s * n + j] = x0.re;
+        XT[(int64_t)i * n + j] = x1.re;
+        if (cplx) {
+          XT[(int64_t)s * n + j + 1] = x0.im;
+          XT[(int64_t)i * n + j + 1] = x1.im;
+        }
+      }
+      i = s - 1;
+    }
+    // normalise (max modulus component -> 1)
+    double mx = 0.0;
+    for (int q = 0; q <= bend; ++q) {
+      double v = fabs(XT[(int64_t)q * n + j]);
+      if (cplx) v += fabs(XT[(int64_t)q * n + j + 1]);
+      mx = fmax(mx, v);
+    }
+    const double sc = (mx > 0.0) ? 1.0 / mx : 1.0;
+    for (int q = 0; q <= bend; ++q) {
+      XT[(int64_t)q * n + j] *= sc;
+      if (cplx) XT[(int64_t)q * n + j + 1] *= sc;
+    }
+  }
+  // rows of Z scaled by the balancing factors: eigenvectors of G are D Z x
+  for (int t = tid; t < n * n; t += NT) {
+    const int c = t / n, r = t % n;
+    ZT[t] *= bal[r];
+    (void)c;
+  }
+#undef HH
+#undef ZZ
+}
+
+}  // namespace vbrdf

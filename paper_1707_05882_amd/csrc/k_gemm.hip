@@ -1,0 +1,95 @@
+// Batched square FP64 GEMM on the CDNA matrix cores: C = op(A) B for every work item.
+//
+// Used for the products of the homogeneous step: FE (Sec. 3.A, eq. 43), E X for the mode vectors
+// (eq. 45) and the back-transformation of the eigenvectors. Each item carries its own n; the grid
+// covers the largest n and surplus tiles exit.
+//
+// Tiling: 64 x 64 output tile per workgroup of 4 waves; each wave owns a 32 x 32 quadrant as 2 x 2
+// v_mfma_f64_16x16x4 tiles; K is staged through LDS 16 at a time. Lane layout of the 16x16x4 FP64
+// MFMA (measured on gfx950 with an in-bounds probe): A element (row = lane % 16, k = lane / 16),
+// B element (k = lane / 16, col = lane % 16), accumulator register v (row = lane / 16 + 4 v,
+// col = lane % 16).
+#include "vbrdf_internal.hpp"
+
+namespace vbrdf {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kGT = 64;  // output tile
+constexpr int kGK = 16;  // K step
+
+__global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB,
+                                               int bufC, const int32_t* status) {
+  const Item it = items[blockIdx.z];
+  if (status[it.layer] != 0) return;
+  const int n = it.n;
+  const int r0 = blockIdx.y * kGT, c0 = blockIdx.x * kGT;
+  if (r0 >= n || c0 >= n) return;
+  const double* A = ws + it.ws + (int64_t)bufA * n * n;
+  const double* B = ws + it.ws + (int64_t)bufB * n * n;
+  double* C = ws + it.ws + (int64_t)bufC * n * n;
+
+  __shared__ double sA[kGT][kGK + 1];
+  __shared__ double sB[kGK][kGT + 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+
+  double4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < n; k0 += kGK) {
+    __syncthreads();
+    // A tile: 64 rows x 16 k
+    for (int t = tid; t < kGT * kGK; t += 256) {
+      int r, k;
+      double v;
+      if (transA) {  // element (row, k) of op(A) lives at A[k * n + row]: rows fastest
+        r = t % kGT;
+        k = t / kGT;
+        v = (r0 + r < n && k0 + k < n) ? A[(int64_t)(k0 + k) * n + r0 + r] : 0.0;
+      } else {
+        k = t % kGK;
+        r = t / kGK;
+        v = (r0 + r < n && k0 + k < n) ? A[(int64_t)(r0 + r) * n + k0 + k] : 0.0;
+      }
+      sA[r][k] = v;
+    }
+    // B tile: 16 k x 64 cols
+    for (int t = tid; t < kGK * kGT; t += 256) {
+      int c = t % kGT, k = t / kGT;
+      sB[k][c] = (k0 + k < n && c0 + c < n) ? B[(int64_t)(k0 + k) * n + c0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[x] = sA[wr + x * 16 + li][kk + lk];
+        b[x] = sB[kk + lk][wc + x * 16 + li];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + wr + x * 16 + lk + 4 * v;
+        const int col = c0 + wc + y * 16 + li;
+        if (row < n && col < n) C[(int64_t)row * n + col] = acc[x][y][v];
+      }
+}
+
+}  // namespace vbrdf

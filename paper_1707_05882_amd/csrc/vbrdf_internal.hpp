@@ -1,0 +1,83 @@
+// Internal descriptors shared by the host planner and the gfx950 kernels.
+//
+// A work item is one (layer, Fourier order m) pair. Every per-order step of the solve runs on one
+// item independently (Sec. 3: the homogeneous solution is computed once per order and serves all
+// incident directions), so kernels are launched over the item table and index their workspace by
+// the item's offset.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vbrdf {
+
+constexpr int kMaxN = 128;          // nodes per hemisphere
+constexpr int kMaxn = 4 * kMaxN;     // Stokes system size 4N
+constexpr int kLdsMaxn = 128;        // largest system kept whole in LDS (128 x 129 doubles)
+constexpr double kOmegaMax = 1.0 - 1e-12;
+
+// Buffers of n*n doubles inside an item's workspace block.
+enum Buf : int {
+  kBufE = 0,   // E~ = M^-1 (I - omega/2 S+ W); later the emergent response R^m
+  kBufF = 1,   // F~ = M^-1 (I - omega/2 S- W); later V = E~ U
+  kBufG = 2,   // G = F~ E~ (eigen input; reduced in place when n > kLdsMaxn)
+  kBufZ = 3,   // Schur vectors (column-major); later S' = U + V D_s
+  kBufX = 4,   // eigenvectors of the quasi-triangular factor; later T' = U + V D_t
+  kBufU = 5,   // eigenvectors U of G (columns)
+  kBufYS = 6,  // U S'^-1
+  kBufYT = 7,  // U T'^-1
+  kNumBuf = 8
+};
+
+struct Layer {
+  int32_t N, L, M, n_dphi;
+  int64_t coef_off;  // doubles, into the caller's packed coefficient array
+  int64_t out_off;   // doubles, into the caller's packed F_r array
+  int64_t quad_off;  // doubles, into the plan's quadrature table (mu[N] then alpha[N])
+  int64_t item0;     // index of this layer's m = 0 item
+};
+
+struct Item {
+  int32_t layer, m, N, L;
+  int32_t n;         // 4N
+  int32_t pad;
+  int64_t ws;        // doubles, start of this item's workspace block
+};
+
+// Per-item extras after the kNumBuf matrices (n doubles each): lam_re, lam_im, balancing factors,
+// Schur block sizes (int), two spare, then d_s (re, im) and d_t (re, im) of the boundary solve;
+// followed by the Legendre table [L][N][3].
+__host__ __device__ inline int64_t extras_off(int n) { return (int64_t)kNumBuf * n * n; }
+__host__ __device__ inline int64_t leg_off(int n) { return extras_off(n) + 10 * (int64_t)n; }
+__host__ __device__ inline int64_t item_doubles(int n, int N, int L) {
+  return leg_off(n) + (int64_t)L * N * 3;
+}
+
+struct SynthTask {
+  int32_t layer, i, q, pad;
+};
+
+constexpr int kSynthMaxM = 512;     // Fourier orders per layer
+constexpr int kSynthMaxPhi = 1024;  // azimuth samples per layer
+
+// ---- kernels (one translation unit each)
+__global__ void k_validate(const Layer* layers, int n_layers, const double* tau, const double* omega,
+                           const double* coef, int32_t* status);
+__global__ void k_legendre(const Item* items, const Layer* layers, const double* quad, double* ws,
+                           const int32_t* status);
+__global__ void k_assemble(const Item* items, const Layer* layers, const double* quad, const double* omega,
+                           const double* coef, double* ws, const int32_t* status);
+__global__ void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB, int bufC,
+                       const int32_t* status);
+__global__ void k_eigen(const Item* items, double* ws, int32_t* status);
+__global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
+__global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
+__global__ void k_rdiv(const Item* items, double* ws, int32_t* status);
+__global__ void k_response(const Item* items, const Layer* layers, const double* quad, double* ws,
+                           const int32_t* status);
+__global__ void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
+                        const double* ws, double* F, const int32_t* status);
+__global__ void k_radiance(const Layer* layers, int layer, int q, const double* quad, const double* F,
+                           double i0, double i1, double i2, double i3, double* I_out);
+
+}  // namespace vbrdf

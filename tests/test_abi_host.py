@@ -1,0 +1,76 @@
+"""Host-side checks of the C-ABI library (no GPU needed): loading, exported symbols, host-only
+entry points and argument validation that fails before any device call."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1707_05882_amd import binding
+from oracle.quadrature import double_gauss
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vbrdf.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(vbrdf_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    syms = declared_symbols()
+    assert len(syms) >= 10
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(binding.EXPORTED)
+
+
+def test_abi_version():
+    assert binding.abi_version() == binding.ABI_VERSION == 1
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 8, 32, 64, 128])
+def test_gauss_nodes_match_library_rule(N):
+    mu, al = binding.gauss_nodes(N)
+    mo, ao = double_gauss(N)
+    assert np.all(np.diff(mu) > 0)
+    assert np.abs(mu - mo).max() < 1e-15
+    assert np.abs(al - ao).max() < 1e-14 * max(1.0, ao.max() * 10)
+    assert abs(al.sum() - 1.0) < 1e-14
+    for k in range(2 * N):
+        assert abs(np.sum(al * mu ** k) - 1.0 / (k + 1)) < 1e-13
+
+
+def test_gauss_nodes_rejects_bad_order():
+    with pytest.raises(binding.VbrdfError) as e:
+        binding.gauss_nodes(0)
+    assert e.value.code == binding.E_INVALID
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(N=[8], L=[4], M=[5], n_dphi=[8]), binding.E_INVALID),       # M > L
+    (dict(N=[0], L=[4], M=[2], n_dphi=[8]), binding.E_INVALID),       # N < 1
+    (dict(N=[8], L=[4], M=[2], n_dphi=[0]), binding.E_INVALID),       # n_dphi < 1
+    (dict(N=[129], L=[4], M=[2], n_dphi=[8]), binding.E_UNSUPPORTED),  # N above the maximum
+    (dict(N=[8], L=[600], M=[600], n_dphi=[8]), binding.E_UNSUPPORTED),  # M above the maximum
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], precision=7), binding.E_UNSUPPORTED),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=4), binding.E_UNSUPPORTED),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace_cap_bytes=1024), binding.E_NOMEM),
+])
+def test_plan_validation(kw, code):
+    with pytest.raises(binding.VbrdfError) as e:
+        binding.Plan(**kw)
+    assert e.value.code == code
+    assert binding.last_error() != ""
+
+
+def test_null_plan_calls_are_rejected():
+    lib = binding.load()
+    assert lib.vbrdf_solve(None, None, None, None, None, None, None) == binding.E_INVALID
+    assert lib.vbrdf_plan_destroy(None) == binding.OK
+    assert lib.vbrdf_plan_output_bytes(None) == 0
+    assert lib.vbrdf_stage_name(0).decode() == "validate"
+    assert lib.vbrdf_stage_name(99) is None

@@ -1,0 +1,187 @@
+"""Parity of the HIP path (called through the C-ABI) with the FP64 CPU oracle.
+
+Tolerance (FP64 path): err = max |F - F_oracle| / max |F_oracle,II| per layer <= 1e-10, the
+normalisation by the largest II element being the scale of the BRDF. Integer outputs (status
+codes) are compared exactly.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dom
+from oracle.quadrature import double_gauss
+from paper_1707_05882_amd import binding
+from paper_1707_05882_amd.api import BRDFSolver, pack_coefficients
+from workloads import rayleigh_coefficients, workload
+from workloads.layers import hg_like_coefficients
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU tests need a ROCm device")
+    binding.load()
+
+
+def rel_err(F, Fo):
+    return float(np.abs(F - Fo).max() / np.abs(Fo[..., 0, 0]).max())
+
+
+def solve(layers):
+    """layers: list of dicts with N, coef, M, P, tau, omega -> (list of F arrays, status)."""
+    s = BRDFSolver([l["N"] for l in layers], [l["coef"].shape[1] for l in layers], [l["M"] for l in layers],
+                   [l["P"] for l in layers])
+    t, w, c = s.upload([l["tau"] for l in layers], [l["omega"] for l in layers], [l["coef"] for l in layers])
+    s.solve_device(t, w, c)
+    torch.cuda.synchronize()
+    return [s.layer(i).cpu().numpy() for i in range(len(layers))], s.status.cpu().numpy(), s
+
+
+def oracle_F(l, orders=False):
+    return dom.brdf(l["coef"], l["tau"], l["omega"], l["N"], l["M"], l["P"], return_orders=orders)
+
+
+def hg(seed, L):
+    return hg_like_coefficients(np.random.default_rng(seed), L)[0]
+
+
+@pytest.fixture(scope="module")
+def particulate():
+    w = workload("particulate")
+    l = dict(N=w.N[0], coef=w.coef[0], M=w.M[0], P=w.n_dphi[0], tau=w.tau[0], omega=w.omega[0])
+    Fo, Ro = oracle_F(l, orders=True)
+    Fs, st, s = solve([l])
+    return l, Fo, Ro, Fs[0], st, s
+
+
+def test_rayleigh_N8():
+    l = dict(N=8, coef=rayleigh_coefficients(), M=3, P=16, tau=1.0, omega=0.9)
+    Fs, st, _ = solve([l])
+    assert st.tolist() == [0]
+    assert rel_err(Fs[0], oracle_F(l)) < TOL
+
+
+def test_particulate_eigenvalues(particulate):
+    """Eigenvalues of F E (1/nu^2) against the squared decaying eigenvalues of the oracle's 8N
+    operator: checks the assembly and the FE product before the eigensolver's vectors are used."""
+    l, _, _, _, st, s = particulate
+    assert st.tolist() == [0]
+    mu, al = double_gauss(l["N"])
+    for m in (0, 1, 17, 40, 63):
+        _, lam = s.plan.inspect(0, m)
+        kap = np.linalg.eigvals(dom.order_operator(l["coef"], l["omega"], m, mu, al))
+        ref = np.sort_complex(kap[kap.real < 0] ** 2)
+        got = np.sort_complex(lam)
+        assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max(), m
+
+
+def test_particulate_orders(particulate):
+    l, _, Ro, _, st, s = particulate
+    scale = max(np.abs(R).max() for R in Ro)
+    for m in (0, 1, 2, 31, 62, 63):
+        R, _ = s.plan.inspect(0, m)
+        assert np.abs(R - Ro[m]).max() < TOL * scale, m
+
+
+def test_particulate_brdf(particulate):
+    l, Fo, _, F, st, _ = particulate
+    assert st.tolist() == [0]
+    assert np.isfinite(F).all()
+    assert rel_err(F, Fo) < TOL
+
+
+def test_uneven_layers_ragged_tiles():
+    """Several layers of different N (ragged 16/64 tiles), L, M and n_dphi in one plan."""
+    layers = [
+        dict(N=3, coef=hg(1, 6), M=6, P=5, tau=0.3, omega=0.7),
+        dict(N=13, coef=hg(2, 20), M=11, P=12, tau=4.0, omega=0.99),
+        dict(N=8, coef=rayleigh_coefficients(), M=3, P=16, tau=1.0, omega=0.9),
+        dict(N=21, coef=hg(3, 30), M=30, P=7, tau=25.0, omega=0.95),
+    ]
+    Fs, st, _ = solve(layers)
+    assert st.tolist() == [0, 0, 0, 0]
+    for l, F in zip(layers, Fs):
+        assert rel_err(F, oracle_F(l)) < TOL, l["N"]
+
+
+def test_system_above_lds_size():
+    """4N = 160 > 128 exercises the global-memory reduction and factorisation path."""
+    l = dict(N=40, coef=hg(4, 10), M=4, P=6, tau=2.0, omega=0.9)
+    Fs, st, _ = solve([l])
+    assert st.tolist() == [0]
+    assert rel_err(Fs[0], oracle_F(l)) < TOL
+
+
+@pytest.mark.parametrize("case", ["N1_isotropic", "single_order", "thin", "thick", "conservative"])
+def test_edge_cases(case):
+    if case == "N1_isotropic":
+        c = np.zeros((6, 1))
+        c[0, 0] = 1.0
+        l = dict(N=1, coef=c, M=1, P=1, tau=0.5, omega=0.8)
+    elif case == "single_order":
+        l = dict(N=6, coef=hg(5, 8), M=1, P=3, tau=1.0, omega=0.9)
+    elif case == "thin":
+        l = dict(N=6, coef=hg(6, 8), M=8, P=8, tau=1e-4, omega=0.9)
+    elif case == "thick":
+        l = dict(N=6, coef=hg(7, 8), M=8, P=8, tau=100.0, omega=0.999)
+    else:
+        l = dict(N=6, coef=hg(8, 8), M=8, P=8, tau=2.0, omega=1.0)
+    Fs, st, _ = solve([l])
+    assert st.tolist() == [0]
+    assert rel_err(Fs[0], oracle_F(l)) < TOL
+
+
+def test_invalid_layers_reported_per_layer():
+    good = dict(N=5, coef=hg(9, 8), M=8, P=4, tau=1.0, omega=0.9)
+    bad_coef = hg(9, 8).copy()
+    bad_coef[0, 0] = 0.5
+    nan_coef = hg(9, 8).copy()
+    nan_coef[2, 3] = np.nan
+    layers = [good, dict(good, tau=-1.0), dict(good, coef=bad_coef), dict(good, omega=1.5), dict(good, coef=nan_coef)]
+    Fs, st, _ = solve(layers)
+    assert st.tolist() == [0, -1, -1, -1, -1]
+    assert rel_err(Fs[0], oracle_F(good)) < TOL
+    for F in Fs[1:]:
+        assert np.isnan(F).all()
+
+
+def test_repeat_solves_are_bitwise_identical():
+    l = dict(N=9, coef=hg(10, 12), M=12, P=6, tau=3.0, omega=0.97)
+    s = BRDFSolver([9], [12], [12], [6])
+    t, w, c = s.upload([l["tau"]], [l["omega"]], [l["coef"]])
+    s.solve_device(t, w, c)
+    a = s.layer(0).clone()
+    s.solve_device(t, w, c)
+    torch.cuda.synchronize()
+    assert torch.equal(a, s.layer(0))
+
+
+def test_radiance_entry_point():
+    l = dict(N=7, coef=hg(11, 10), M=10, P=9, tau=1.5, omega=0.9)
+    Fs, st, s = solve([l])
+    mu, _ = double_gauss(7)
+    I0 = [1.0, 0.3, -0.2, 0.1]
+    out = torch.empty(7 * 9 * 4, dtype=torch.float64, device="cuda")
+    s.plan.radiance(s.F, 0, 4, I0, out, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ref = mu[4] * np.einsum("ikrp,p->ikr", Fs[0][:, 4], np.array(I0))
+    assert np.abs(out.cpu().numpy().reshape(7, 9, 4) - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+def test_stage_timing():
+    plan = binding.Plan([8], [6], [6], [8], flags=binding.FLAG_STAGE_TIMING)
+    dev = "cuda"
+    c = torch.as_tensor(pack_coefficients([hg(12, 6)]), device=dev)
+    t = torch.tensor([1.0], dtype=torch.float64, device=dev)
+    w = torch.tensor([0.9], dtype=torch.float64, device=dev)
+    F = torch.empty(plan.output_bytes() // 8, dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    plan.solve(t, w, c, F, st, torch.cuda.current_stream().cuda_stream)
+    times = plan.stage_times()
+    assert list(times)[0] == "validate" and "eigen" in times and len(times) == 12
+    assert all(v >= 0 for v in times.values())
