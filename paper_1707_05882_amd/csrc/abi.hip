@@ -274,7 +274,7 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
   mark();
   k_eigen<<<ni, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufU, layer_status);  // U = (D Z) X
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufU, layer_status);  // U = Z X
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufF, layer_status);  // V = E~ U
   mark();

@@ -5,15 +5,17 @@
 // one workgroup solves one (layer, order) matrix and all orders of all layers run in one launch.
 //
 // Steps (all in FP64):
-//   1. diagonal balancing by powers of two (exact similarity; the matrix is graded by 1/mu^2),
-//   2. Householder reduction to upper Hessenberg form, accumulating the orthogonal factor Z,
-//   3. implicit double-shift (Francis) QR to real Schur form T = Z^T H Z with deflation by the
+//   1. Householder reduction to upper Hessenberg form, accumulating the orthogonal factor Z,
+//   2. implicit double-shift (Francis) QR to real Schur form T = Z^T H Z with deflation by the
 //      Ahues-Tisseur criterion, exceptional shifts every 10 stagnant sweeps, a real shift pair
 //      replaced by the eigenvalue closer to the corner used twice, and after 40 stagnant sweeps
 //      (a cluster of nearly equal eigenvalues) a normwise deflation |h| <= ulp ||H||_F,
-//   4. eigenvectors of the quasi-triangular T by back-substitution (complex arithmetic only for
-//      complex pairs), normalised, and Z scaled by the balancing factors.
-// The caller then forms U = (D Z) X_T with a GEMM. Output convention: for a complex pair stored at
+//   3. eigenvectors of the quasi-triangular T by back-substitution (complex arithmetic only for
+//      complex pairs), normalised.
+// The matrix is not balanced: F E = M^-1 X- M^-1 X+ is graded by the 1/mu factors, and a diagonal
+// power-of-two balancing loses about two digits on its smallest (diffusion-mode) eigenvalues,
+// which dominate the response; without it the eigenpairs reach about 1e-11 relative.
+// The caller then forms U = Z X_T with a GEMM. Output convention: for a complex pair stored at
 // (j, j+1) with Im lambda_j > 0, U[:, j] + i U[:, j+1] is the eigenvector of lambda_j.
 //
 // H is kept in LDS (row stride n + 1) when n <= 128 and reduced in place in global memory
@@ -107,7 +109,6 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
   double* ex = base + extras_off(n);
   double* lre = ex;
   double* lim = ex + n;
-  double* bal = ex + 2 * n;
   int* blk = reinterpret_cast<int*>(ex + 3 * n);
 
   __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1)];
@@ -125,47 +126,11 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
 #define HH(r, c) H[(int64_t)(r) * ld + (c)]
 #define ZZ(r, c) ZT[(int64_t)(c) * n + (r)]
 
-  // ---- load, Z = I, balance factors = 1
+  // ---- load, Z = I
   if (in_lds)
     for (int t = tid; t < n * n; t += NT) HH(t / n, t % n) = G[t];
   for (int t = tid; t < n * n; t += NT) ZT[t] = ((t / n) == (t % n)) ? 1.0 : 0.0;
-  for (int i = tid; i < n; i += NT) bal[i] = 1.0;
   __syncthreads();
-
-  // ---- 1. balancing (simultaneous power-of-two row/column scalings until no gain)
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    if (tid == 0) sctl[0] = 0;
-    __syncthreads();
-    for (int i = tid; i < n; i += NT) {
-      double c = 0.0, r = 0.0;
-      for (int j = 0; j < n; ++j) {
-        if (j == i) continue;
-        c += fabs(HH(j, i));
-        r += fabs(HH(i, j));
-      }
-      double f = 1.0;
-      if (c > 0.0 && r > 0.0) {
-        int e = (int)rint(0.5 * log2(r / c));
-        e = max(-20, min(20, e));
-        if (e != 0) {
-          double ff = ldexp(1.0, e);
-          if (c * ff + r / ff < 0.95 * (c + r)) {
-            f = ff;
-            sctl[0] = 1;
-          }
-        }
-      }
-      sv[i] = f;
-    }
-    __syncthreads();
-    if (sctl[0] == 0) break;
-    for (int t = tid; t < n * n; t += NT) {
-      int r = t / n, c = t % n;
-      HH(r, c) *= sv[c] / sv[r];
-    }
-    for (int i = tid; i < n; i += NT) bal[i] *= sv[i];
-    __syncthreads();
-  }
 
   // Frobenius norm (invariant under the orthogonal similarities that follow): backstop scale
   // for deflation in clusters of nearly equal eigenvalues where the local test cannot be met.
@@ -182,7 +147,7 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
   const double hnorm = sxyz[0];
   __syncthreads();
 
-  // ---- 2. Householder reduction to Hessenberg form, Z accumulated
+  // ---- 1. Householder reduction to Hessenberg form, Z accumulated
   for (int k = 0; k + 2 < n; ++k) {
     double part = 0.0;
     for (int i = k + 2 + tid; i < n; i += NT) part += HH(i, k) * HH(i, k);
@@ -217,7 +182,7 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
     __syncthreads();
   }
 
-  // ---- 3. Francis double-shift QR to real Schur form
+  // ---- 2. Francis double-shift QR to real Schur form
   if (tid == 0) {
     sctl[1] = n - 1;  // active bottom index hh
     sctl[2] = 0;      // iterations since last deflation
@@ -265,21 +230,30 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
         const double a = HH(hh - 1, hh - 1), b = HH(hh - 1, hh), c = HH(hh, hh - 1), d = HH(hh, hh);
         const double p = 0.5 * (a - d), bc = b * c, disc = p * p + bc;
         if (disc >= 0.0) {
+          // real pair: rotate the block to upper triangular form (first column = eigenvector of
+          // the first eigenvalue) so that both become 1x1 blocks; applied by all threads below
           const double zz = p + copysign(sqrt(disc), p);
-          lre[hh - 1] = d + zz;
-          lre[hh] = (zz != 0.0) ? d - bc / zz : d;
-          lim[hh - 1] = 0.0;
-          lim[hh] = 0.0;
+          const double l1 = d + zz;
+          double v0 = b, v1 = l1 - a;
+          const double w0 = l1 - d, w1 = c;
+          if (fabs(w0) + fabs(w1) > fabs(v0) + fabs(v1)) {
+            v0 = w0;
+            v1 = w1;
+          }
+          const double nv = hypot(v0, v1);
+          sxyz[0] = (nv > 0.0) ? v0 / nv : 1.0;
+          sxyz[1] = (nv > 0.0) ? v1 / nv : 0.0;
+          sctl[4] = 2;
         } else {
           lre[hh - 1] = lre[hh] = 0.5 * (a + d);
           lim[hh - 1] = sqrt(-disc);
           lim[hh] = -sqrt(-disc);
+          blk[hh - 1] = 2;
+          blk[hh] = 0;
+          sctl[1] = hh - 2;
+          sctl[2] = 0;
+          sctl[4] = 0;
         }
-        blk[hh - 1] = 2;
-        blk[hh] = 0;
-        sctl[1] = hh - 2;
-        sctl[2] = 0;
-        sctl[4] = 0;
       } else {
         const int its = ++sctl[2];
         const int tot = ++sctl[3];
@@ -338,6 +312,40 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
     }
     __syncthreads();
     if (sctl[4] == 0) continue;  // deflated (or failed: hh < 0 ends the loop)
+    if (sctl[4] == 2) {          // split a real 2x2 block with the rotation [[cs, -sn], [sn, cs]]
+      const double cs = sxyz[0], sn = sxyz[1];
+      const int h1 = hh - 1;
+      for (int c = h1 + tid; c < n; c += NT) {
+        const double x = HH(h1, c), y = HH(hh, c);
+        HH(h1, c) = cs * x + sn * y;
+        HH(hh, c) = -sn * x + cs * y;
+      }
+      __syncthreads();
+      for (int r = tid; r < n; r += NT) {
+        if (r <= hh) {
+          const double x = HH(r, h1), y = HH(r, hh);
+          HH(r, h1) = cs * x + sn * y;
+          HH(r, hh) = -sn * x + cs * y;
+        }
+        const double zx = ZZ(r, h1), zy = ZZ(r, hh);
+        ZZ(r, h1) = cs * zx + sn * zy;
+        ZZ(r, hh) = -sn * zx + cs * zy;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        HH(hh, h1) = 0.0;
+        lre[h1] = HH(h1, h1);
+        lre[hh] = HH(hh, hh);
+        lim[h1] = 0.0;
+        lim[hh] = 0.0;
+        blk[h1] = 1;
+        blk[hh] = 1;
+        sctl[1] = hh - 2;
+        sctl[2] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
 
     const int lo = sctl[6];
     for (int k = lo; k <= hh - 1; ++k) {
@@ -431,13 +439,19 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
     return;
   }
 
-  // ---- 4. eigenvectors of the quasi-triangular factor by back-substitution
+  // ---- 3. eigenvectors of the quasi-triangular factor by back-substitution
   for (int j = tid; j < n; j += NT) {
     const double wr = lre[j], wi = lim[j];
     if (wi < 0.0) continue;  // second member of a complex pair: written by j - 1
     const int b0 = (blk[j] == 0) ? j - 1 : j;   // own block start
     const int bend = (blk[b0] == 2) ? b0 + 1 : b0;
     const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
+    // Eigenvalues closer than a few ulp ||G|| cannot be told apart: a diagonal entry (or 2x2 block)
+    // that close to lambda is another copy of the same multiple eigenvalue of a diagonalisable
+    // matrix (e.g. the unscattered Stokes components at one node, lambda = 1/mu^2), and its Schur
+    // coupling is rounding noise. Its component is set to zero instead of dividing the noise by a
+    // guarded pivot, which would make the copies' eigenvectors parallel.
+    const double same = 8.0 * kUlp * hnorm;
     const bool cplx = wi > 0.0;
     const Cx lam{wr, wi};
     for (int i = bend + 1; i < n; ++i) {
@@ -486,10 +500,17 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
         }
       }
       if (s == i) {
-        const Cx dd = cguard(csub(Cx{HH(i, i), 0.0}, lam), smin);
-        const Cx xi = cdiv(r0, dd);
+        const Cx d0 = csub(Cx{HH(i, i), 0.0}, lam);
+        const Cx xi = (cabs1(d0) <= same) ? Cx{0.0, 0.0} : cdiv(r0, cguard(d0, smin));
         XT[(int64_t)i * n + j] = xi.re;
         if (cplx) XT[(int64_t)i * n + j + 1] = xi.im;
+      } else if (cabs1(csub(Cx{lre[s], lim[s]}, lam)) <= same || cabs1(csub(Cx{lre[i], lim[i]}, lam)) <= same) {
+        XT[(int64_t)s * n + j] = 0.0;
+        XT[(int64_t)i * n + j] = 0.0;
+        if (cplx) {
+          XT[(int64_t)s * n + j + 1] = 0.0;
+          XT[(int64_t)i * n + j + 1] = 0.0;
+        }
       } else {
         Cx x0, x1;
         csolve2(csub(Cx{HH(s, s), 0.0}, lam), Cx{HH(s, i), 0.0}, Cx{HH(i, s), 0.0},
@@ -515,12 +536,6 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
       XT[(int64_t)q * n + j] *= sc;
       if (cplx) XT[(int64_t)q * n + j + 1] *= sc;
     }
-  }
-  // rows of Z scaled by the balancing factors: eigenvectors of G are D Z x
-  for (int t = tid; t < n * n; t += NT) {
-    const int c = t / n, r = t % n;
-    ZT[t] *= bal[r];
-    (void)c;
   }
 #undef HH
 #undef ZZ
