@@ -20,10 +20,10 @@ using namespace vbrdf;
 
 namespace {
 
-constexpr int kNumStages = 12;
+constexpr int kNumStages = 13;
 constexpr int kTimedSolves = 256;  // solves whose stage events are kept between queries
-const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen", "gemm_U",
-                                             "gemm_V", "colscal", "bcbuild", "rdiv", "response", "synth"};
+const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen",   "gemm_U", "gemm_V",
+                                             "vfix",     "colscal",  "bcbuild",  "rdiv",    "response", "synth"};
 
 thread_local std::string g_err;
 
@@ -276,7 +276,9 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufU, layer_status);  // U = Z X
   mark();
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufF, layer_status);  // V = E~ U
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, layer_status);  // V = E~ U
+  mark();
+  k_vfix<<<ni, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
   k_colscal<<<dim3((mn + 63) / 64, ni), 64, 0, s>>>(p->items_d, tau, p->ws_d, layer_status);
   mark();

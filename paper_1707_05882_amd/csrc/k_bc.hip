@@ -86,7 +86,7 @@ __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status) 
   if (i >= n || j >= n) return;
   double* base = ws + it.ws;
   const double* U = base + (int64_t)kBufU * n * n;
-  const double* V = base + (int64_t)kBufF * n * n;
+  const double* V = base + (int64_t)kBufG * n * n;
   double* S = base + (int64_t)kBufZ * n * n;
   double* T = base + (int64_t)kBufX * n * n;
   const double* ex = base + extras_off(n);
@@ -140,48 +140,20 @@ __device__ inline void block_argmax(double v, int idx, double* sv, int* si) {
   __syncthreads();
 }
 
-// LU factorisation with partial pivoting of A (S' or T') and the right division Y = U A^-1.
-// blockIdx.y selects S' (0) or T' (1). With P^T A = L Uu (row perm[k] of A at position k),
-// Y A = U becomes W L Uu = U for W = Y P, i.e. Y[:, perm[k]] = W[:, k].
-__global__ __launch_bounds__(256) void k_rdiv(const Item* items, double* ws, int32_t* status) {
-  const Item it = items[blockIdx.x];
-  if (status[it.layer] != 0) return;
-  const int n = it.n;
-  const int which = blockIdx.y;
-  double* base = ws + it.ws;
-  double* Ag = base + (int64_t)(which == 0 ? kBufZ : kBufX) * n * n;
-  const double* U = base + (int64_t)kBufU * n * n;
-  double* Y = base + (int64_t)(which == 0 ? kBufYS : kBufYT) * n * n;
-
-  __shared__ double smem[kLdsMaxn * (kLdsMaxn + 1) + kRows * (kLdsMaxn + 1) > kRows * (kMaxn + 1)
-                            ? kLdsMaxn * (kLdsMaxn + 1) + kRows * (kLdsMaxn + 1)
-                            : kRows * (kMaxn + 1)];
-  __shared__ int perm[kMaxn];
-  __shared__ double invd[kMaxn];
-  __shared__ double redv[8];
-  __shared__ int redi[8];
-  __shared__ int sflag;
-
+// In-place LU factorisation with partial pivoting, P^T A = L Uu (row perm[k] of the original at
+// position k), unit L below the diagonal, invd[k] = 1 / Uu_kk. A has row stride ld and lives in LDS
+// or global memory (the caller passes a pointer derived from the __shared__ array so the accesses
+// compile to LDS instructions). Returns false (uniformly) on a zero or non-finite pivot.
+__device__ __forceinline__ bool lu_factor(double* A, int64_t ld, int n, int* perm, double* invd, double* redv,
+                                          int* redi) {
   const int tid = threadIdx.x, NT = blockDim.x;
-  const bool in_lds = n <= kLdsMaxn;
-  double* A = in_lds ? smem : Ag;
-  const int64_t ld = in_lds ? n + 1 : n;
-  const int ldb = n + 1;  // padded: rows of the right-hand-side tile fall in distinct LDS banks
-  double* B = in_lds ? smem + kLdsMaxn * (kLdsMaxn + 1) : smem;  // [kRows][n + 1]
-#define AA(r, c) A[(int64_t)(r) * ld + (c)]
-#define BB(r, c) B[(int64_t)(r) * ldb + (c)]
-
-  if (in_lds)
-    for (int t = tid; t < n * n; t += NT) AA(t / n, t % n) = Ag[t];
   for (int i = tid; i < n; i += NT) perm[i] = i;
-  if (tid == 0) sflag = 0;
   __syncthreads();
-
   for (int k = 0; k < n; ++k) {
     double best = -1.0;
     int bi = k;
     for (int i = k + tid; i < n; i += NT) {
-      const double v = fabs(AA(i, k));
+      const double v = fabs(A[(int64_t)i * ld + k]);
       if (v > best) {
         best = v;
         bi = i;
@@ -190,15 +162,12 @@ __global__ __launch_bounds__(256) void k_rdiv(const Item* items, double* ws, int
     block_argmax(best, bi, redv, redi);
     const int p = redi[0];
     const double pv = redv[0];
-    if (!(pv > 0.0) || !isfinite(pv)) {
-      if (tid == 0) sflag = 1;
-      break;  // uniform: every thread read the same pivot
-    }
+    if (!(pv > 0.0) || !isfinite(pv)) return false;
     if (p != k) {
       for (int c = tid; c < n; c += NT) {
-        const double t = AA(k, c);
-        AA(k, c) = AA(p, c);
-        AA(p, c) = t;
+        const double t = A[(int64_t)k * ld + c];
+        A[(int64_t)k * ld + c] = A[(int64_t)p * ld + c];
+        A[(int64_t)p * ld + c] = t;
       }
       if (tid == 0) {
         const int t = perm[k];
@@ -207,24 +176,45 @@ __global__ __launch_bounds__(256) void k_rdiv(const Item* items, double* ws, int
       }
     }
     __syncthreads();
-    const double inv = 1.0 / AA(k, k);
-    for (int i = k + 1 + tid; i < n; i += NT) AA(i, k) *= inv;
+    const double inv = 1.0 / A[(int64_t)k * ld + k];
+    for (int i = k + 1 + tid; i < n; i += NT) A[(int64_t)i * ld + k] *= inv;
     if (tid == 0) invd[k] = inv;
     __syncthreads();
     const int m = n - k - 1;
     for (int t = tid; t < m * m; t += NT) {
       const int i = k + 1 + t / m, c = k + 1 + t % m;
-      AA(i, c) -= AA(i, k) * AA(k, c);
+      A[(int64_t)i * ld + c] -= A[(int64_t)i * ld + k] * A[(int64_t)k * ld + c];
     }
     __syncthreads();
   }
-  __syncthreads();
-  if (sflag) {
+  return true;
+}
+
+constexpr int kLuLds = kLdsMaxn * (kLdsMaxn + 1);                 // LDS matrix
+constexpr int kRhsLds = kRows * (kMaxn + 1);                       // LDS right-hand-side tile
+constexpr int kBcLds = (kLuLds + kRows * (kLdsMaxn + 1) > kRhsLds) ? kLuLds + kRows * (kLdsMaxn + 1) : kRhsLds;
+
+// Y = U A^-1 for one item: factor A (in LDS when kLds), then right-divide kRows rows of U at a time.
+template <bool kLds>
+__device__ __forceinline__ void rdiv_body(const Item& it, double* Ag, const double* __restrict__ U,
+                                          double* __restrict__ Y, int32_t* status, double* smem, int* perm,
+                                          double* invd, double* redv, int* redi) {
+  const int n = it.n;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  double* A = kLds ? smem : Ag;
+  const int64_t ld = kLds ? n + 1 : n;
+  const int ldb = n + 1;  // padded: rows of the right-hand-side tile fall in distinct LDS banks
+  double* B = kLds ? smem + kLuLds : smem;  // [kRows][n + 1]
+  if (kLds) {
+    for (int t = tid; t < n * n; t += NT) A[(int64_t)(t / n) * ld + (t % n)] = Ag[t];
+    __syncthreads();
+  }
+  if (!lu_factor(A, ld, n, perm, invd, redv, redi)) {
     if (tid == 0) status[it.layer] = -5;
     return;
   }
-
-  // right division, kRows rows of U per pass
+#define AA(r, c) A[(int64_t)(r) * ld + (c)]
+#define BB(r, c) B[(int64_t)(r) * ldb + (c)]
   for (int r0 = 0; r0 < n; r0 += kRows) {
     const int nr = min(kRows, n - r0);
     for (int t = tid; t < kRows * n; t += NT) {
@@ -261,8 +251,163 @@ __global__ __launch_bounds__(256) void k_rdiv(const Item* items, double* ws, int
     }
     __syncthreads();
   }
-#undef BB
 #undef AA
+#undef BB
+}
+
+// LU factorisation with partial pivoting of A (S' or T') and the right division Y = U A^-1.
+// blockIdx.y selects S' (0) or T' (1). With P^T A = L Uu (row perm[k] of A at position k),
+// Y A = U becomes W L Uu = U for W = Y P, i.e. Y[:, perm[k]] = W[:, k].
+__global__ __launch_bounds__(256) void k_rdiv(const Item* items, double* ws, int32_t* status) {
+  const Item it = items[blockIdx.x];
+  if (status[it.layer] != 0) return;
+  const int n = it.n;
+  const int which = blockIdx.y;
+  double* base = ws + it.ws;
+  double* Ag = base + (int64_t)(which == 0 ? kBufZ : kBufX) * n * n;
+  const double* U = base + (int64_t)kBufU * n * n;
+  double* Y = base + (int64_t)(which == 0 ? kBufYS : kBufYT) * n * n;
+  __shared__ double smem[kBcLds];
+  __shared__ int perm[kMaxn];
+  __shared__ double invd[kMaxn];
+  __shared__ double redv[8];
+  __shared__ int redi[8];
+  if (n <= kLdsMaxn)
+    rdiv_body<true>(it, Ag, U, Y, status, smem, perm, invd, redv, redi);
+  else
+    rdiv_body<false>(it, Ag, U, Y, status, smem, perm, invd, redv, redi);
+}
+
+// Columns of V = E~ U that lost more than ~7 digits to cancellation (the conservation mode of
+// order 0 when omega is near 1: E~ u is then O(1 - omega) while its terms are O(||E~|| ||u||)) are
+// recomputed from F~ E~ U = U Lambda as V = F~^-1 U Lambda, which has no such cancellation. For a
+// complex pair the 2x2 real block of Lambda is applied.
+constexpr double kVfixRatio = 1e-7;
+
+template <bool kLds>
+__device__ __forceinline__ void vfix_body(const Item& it, double* base, int32_t* status, double* smem, int* perm,
+                                          double* invd, double* redv, int* redi, int* flag, double* enorm) {
+  const int n = it.n;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const double* E = base + (int64_t)kBufE * n * n;
+  double* Fg = base + (int64_t)kBufF * n * n;
+  const double* U = base + (int64_t)kBufU * n * n;
+  double* V = base + (int64_t)kBufG * n * n;
+  const double* lre = base + extras_off(n);
+  const double* lim = lre + n;
+  // ||E~||_inf
+  double part = 0.0;
+  for (int r = tid; r < n; r += NT) {
+    double s = 0.0;
+    for (int c = 0; c < n; ++c) s += fabs(E[(int64_t)r * n + c]);
+    part = fmax(part, s);
+  }
+  if (tid == 0) *enorm = 0.0;
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1)
+    if (o < (int)blockDim.x) part = fmax(part, __shfl_xor(part, o));
+  if ((tid & 63) == 0) redv[tid >> 6] = part;
+  __syncthreads();
+  if (tid == 0) {
+    double e = 0.0;
+    for (int w = 0; w < (NT + 63) / 64; ++w) e = fmax(e, redv[w]);
+    *enorm = e;
+  }
+  __syncthreads();
+  const double en = *enorm;
+  int any = 0;
+  for (int j = tid; j < n; j += NT) {
+    double nu = 0.0, nv = 0.0;
+    for (int r = 0; r < n; ++r) {
+      nu = fmax(nu, fabs(U[(int64_t)r * n + j]));
+      nv = fmax(nv, fabs(V[(int64_t)r * n + j]));
+    }
+    const int f = (nv < kVfixRatio * en * nu) ? 1 : 0;
+    flag[j] = f;
+    any |= f;
+  }
+  __syncthreads();
+  // pairs are flagged together
+  for (int j = tid; j < n; j += NT) {
+    if (lim[j] > 0.0 && j + 1 < n && (flag[j] | flag[j + 1])) any = 1;
+  }
+  for (int o = 32; o > 0; o >>= 1)
+    if (o < (int)blockDim.x) any |= __shfl_xor(any, o);
+  if ((tid & 63) == 0) redi[tid >> 6] = any;
+  __syncthreads();
+  int need = 0;
+  for (int w = 0; w < (NT + 63) / 64; ++w) need |= redi[w];
+  __syncthreads();
+  if (!need) return;  // uniform
+  for (int j = tid; j < n; j += NT) {
+    if (lim[j] > 0.0 && j + 1 < n && (flag[j] | flag[j + 1])) {
+      flag[j] = 1;
+      flag[j + 1] = 1;
+    }
+  }
+  __syncthreads();
+  double* A = kLds ? smem : Fg;
+  const int64_t ld = kLds ? n + 1 : n;
+  if (kLds) {
+    for (int t = tid; t < n * n; t += NT) A[(int64_t)(t / n) * ld + (t % n)] = Fg[t];
+    __syncthreads();
+  }
+  if (!lu_factor(A, ld, n, perm, invd, redv, redi)) {
+    if (tid == 0) status[it.layer] = -5;
+    return;
+  }
+  double* w = kLds ? smem + kLuLds : smem + 0;  // [n] work vector (global path: A is in Fg)
+  double* w2 = w + kMaxn;
+  for (int j = 0; j < n; ++j) {
+    if (!flag[j]) continue;  // uniform: flag is shared
+    if (lim[j] < 0.0) continue;  // second column of a pair: handled with the first
+    const bool pair = lim[j] > 0.0;
+    for (int col = 0; col < (pair ? 2 : 1); ++col) {
+      double* x = col ? w2 : w;
+      // x = P^T u
+      for (int r = tid; r < n; r += NT) x[r] = U[(int64_t)perm[r] * n + j + col];
+      __syncthreads();
+      for (int k = 0; k + 1 < n; ++k) {  // L y = P^T u
+        const double xk = x[k];
+        for (int r = k + 1 + tid; r < n; r += NT) x[r] -= A[(int64_t)r * ld + k] * xk;
+        __syncthreads();
+      }
+      for (int k = n - 1; k >= 0; --k) {  // Uu z = y
+        if (tid == 0) x[k] *= invd[k];
+        __syncthreads();
+        const double xk = x[k];
+        for (int r = tid; r < k; r += NT) x[r] -= A[(int64_t)r * ld + k] * xk;
+        __syncthreads();
+      }
+    }
+    const double a = lre[j], b = lim[j];
+    for (int r = tid; r < n; r += NT) {
+      if (pair) {
+        V[(int64_t)r * n + j] = a * w[r] - b * w2[r];
+        V[(int64_t)r * n + j + 1] = b * w[r] + a * w2[r];
+      } else {
+        V[(int64_t)r * n + j] = a * w[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_vfix(const Item* items, double* ws, int32_t* status) {
+  const Item it = items[blockIdx.x];
+  if (status[it.layer] != 0) return;
+  double* base = ws + it.ws;
+  __shared__ double smem[kBcLds];
+  __shared__ int perm[kMaxn];
+  __shared__ double invd[kMaxn];
+  __shared__ double redv[8];
+  __shared__ int redi[8];
+  __shared__ int flag[kMaxn];
+  __shared__ double enorm;
+  if (it.n <= kLdsMaxn)
+    vfix_body<true>(it, base, status, smem, perm, invd, redv, redi, flag, &enorm);
+  else
+    vfix_body<false>(it, base, status, smem, perm, invd, redv, redi, flag, &enorm);
 }
 
 // R^m = Delta (Y_S + Y_T - I) R0, written over kBufE.

@@ -19,8 +19,8 @@ constexpr double kOmegaMax = 1.0 - 1e-12;
 // Buffers of n*n doubles inside an item's workspace block.
 enum Buf : int {
   kBufE = 0,   // E~ = M^-1 (I - omega/2 S+ W); later the emergent response R^m
-  kBufF = 1,   // F~ = M^-1 (I - omega/2 S- W); later V = E~ U
-  kBufG = 2,   // G = F~ E~ (eigen input; reduced in place when n > kLdsMaxn)
+  kBufF = 1,   // F~ = M^-1 (I - omega/2 S- W)
+  kBufG = 2,   // G = F~ E~ (eigen input; reduced in place when n > kLdsMaxn); later V = E~ U
   kBufZ = 3,   // Schur vectors (column-major); later S' = U + V D_s
   kBufX = 4,   // eigenvectors of the quasi-triangular factor; later T' = U + V D_t
   kBufU = 5,   // eigenvectors U of G (columns)
@@ -70,6 +70,7 @@ __global__ void k_assemble(const Item* items, const Layer* layers, const double*
 __global__ void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB, int bufC,
                        const int32_t* status);
 __global__ void k_eigen(const Item* items, double* ws, int32_t* status);
+__global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
 __global__ void k_rdiv(const Item* items, double* ws, int32_t* status);

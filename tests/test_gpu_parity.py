@@ -183,5 +183,5 @@ def test_stage_timing():
     st = torch.empty(1, dtype=torch.int32, device=dev)
     plan.solve(t, w, c, F, st, torch.cuda.current_stream().cuda_stream)
     times = plan.stage_times()
-    assert list(times)[0] == "validate" and "eigen" in times and len(times) == 12
+    assert list(times)[0] == "validate" and "eigen" in times and "vfix" in times and len(times) == 13
     assert all(v >= 0 for v in times.values())
