@@ -19,8 +19,12 @@
 // (j, j+1) with Im lambda_j > 0, U[:, j] + i U[:, j+1] is the eigenvector of lambda_j.
 //
 // H is kept in LDS (row stride n + 1) when n <= 128 and reduced in place in global memory
-// otherwise. During a QR sweep the reflectors are kept in LDS and applied to Z afterwards, each
-// thread streaming along its own rows of Z with a three-element window.
+// otherwise (the body is instantiated for both, so LDS-resident H uses LDS instructions). A QR
+// sweep touches only a 3-row / 3-column window per bulge step, too little work for a workgroup
+// barrier per step: wave 0 alone runs the deflation scan, the shift choice and the bulge chase,
+// its lanes kept in step by wave-level ordering (every lane computes the reflector itself). The
+// sweep's reflectors are kept in LDS and all waves then apply them to Z, each thread streaming
+// along its own rows of Z with a three-element window.
 #include "vbrdf_internal.hpp"
 
 namespace vbrdf {
@@ -45,16 +49,6 @@ __device__ inline double block_sum(double v, double* sred) {
   double r = 0.0;
   const int nw = (blockDim.x + 63) >> 6;
   for (int w = 0; w < nw; ++w) r += sred[w];
-  __syncthreads();
-  return r;
-}
-__device__ inline int block_max(int v, int* sred) {
-  v = wave_max(v);
-  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int r = sred[0];
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int w = 1; w < nw; ++w) r = max(r, sred[w]);
   __syncthreads();
   return r;
 }
@@ -98,36 +92,38 @@ __device__ inline void csolve2(Cx a, Cx b, Cx c, Cx d, Cx r0, Cx r1, double smin
   }
 }
 
-__global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, int32_t* status) {
-  const Item it = items[blockIdx.x];
-  if (status[it.layer] != 0) return;
+// Orders LDS (and global) accesses of different lanes of one wave: a wave's memory operations
+// execute in order, so a compiler scheduling barrier is all the hand-off needs.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Action codes of the QR driver (sctl[4]).
+enum : int { kActDeflated = 0, kActSweep = 1, kActRotate = 2, kActStop = 3 };
+
+template <bool kLds>
+__device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t* status, double* sH, double* sv,
+                                           double* srefl, double* sred, int* sredi, int* sctl, double* sxyz) {
   const int n = it.n;
-  double* base = ws + it.ws;
   double* G = base + (int64_t)kBufG * n * n;
-  double* ZT = base + (int64_t)kBufZ * n * n;  // Z(r, c) = ZT[c * n + r]
-  double* XT = base + (int64_t)kBufX * n * n;  // eigenvector j, component i at XT[i * n + j]
+  double* __restrict__ ZT = base + (int64_t)kBufZ * n * n;  // Z(r, c) = ZT[c * n + r]
+  double* __restrict__ XT = base + (int64_t)kBufX * n * n;  // eigenvector j, component i at XT[i * n + j]
   double* ex = base + extras_off(n);
   double* lre = ex;
   double* lim = ex + n;
   int* blk = reinterpret_cast<int*>(ex + 3 * n);
 
-  __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1)];
-  __shared__ double sv[kMaxn];
-  __shared__ double srefl[3 * kMaxn];
-  __shared__ double sred[8];
-  __shared__ int sredi[8];
-  __shared__ int sctl[8];
-  __shared__ double sxyz[3];
-
-  const int tid = threadIdx.x, NT = blockDim.x;
-  const bool in_lds = n <= kLdsMaxn;
-  double* H = in_lds ? sH : G;
-  const int64_t ld = in_lds ? n + 1 : n;
+  const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63;
+  const bool wave0 = tid < 64;
+  const int W0 = NT < 64 ? NT : 64;  // lanes of wave 0
+  double* H = kLds ? sH : G;
+  const int64_t ld = kLds ? n + 1 : n;
 #define HH(r, c) H[(int64_t)(r) * ld + (c)]
 #define ZZ(r, c) ZT[(int64_t)(c) * n + (r)]
 
   // ---- load, Z = I
-  if (in_lds)
+  if (kLds)
     for (int t = tid; t < n * n; t += NT) HH(t / n, t % n) = G[t];
   for (int t = tid; t < n * n; t += NT) ZT[t] = ((t / n) == (t % n)) ? 1.0 : 0.0;
   __syncthreads();
@@ -164,25 +160,34 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
     for (int i = tid; i < len; i += NT) HH(k + 1 + i, k) = (i == 0) ? beta : 0.0;
     for (int c = k + 1 + tid; c < n; c += NT) {  // left: (I - tau v v^T) H
       double w = 0.0;
+#pragma unroll 8
       for (int i = 0; i < len; ++i) w += sv[i] * HH(k + 1 + i, c);
       w *= tau;
+#pragma unroll 8
       for (int i = 0; i < len; ++i) HH(k + 1 + i, c) -= sv[i] * w;
     }
     __syncthreads();
     for (int r = tid; r < n; r += NT) {  // right: H (I - tau v v^T), and Z likewise
       double y = 0.0;
+#pragma unroll 8
       for (int i = 0; i < len; ++i) y += HH(r, k + 1 + i) * sv[i];
       y *= tau;
+#pragma unroll 8
       for (int i = 0; i < len; ++i) HH(r, k + 1 + i) -= y * sv[i];
       double yz = 0.0;
+#pragma unroll 8
       for (int i = 0; i < len; ++i) yz += ZZ(r, k + 1 + i) * sv[i];
       yz *= tau;
+#pragma unroll 8
       for (int i = 0; i < len; ++i) ZZ(r, k + 1 + i) -= yz * sv[i];
     }
     __syncthreads();
   }
 
   // ---- 2. Francis double-shift QR to real Schur form
+  // Wave 0 runs the deflation scan, the shift choice and each sweep's bulge chase on its own
+  // (lane-synchronous, no workgroup barrier inside a sweep; every lane computes the reflector);
+  // all waves then apply the sweep's reflectors to Z.
   if (tid == 0) {
     sctl[1] = n - 1;  // active bottom index hh
     sctl[2] = 0;      // iterations since last deflation
@@ -191,130 +196,226 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
   }
   __syncthreads();
   while (true) {
-    const int hh = sctl[1];
-    if (hh < 0) break;
-    // parallel deflation scan: largest k in [1, hh] with a negligible subdiagonal
-    int cand = 0;
-    const bool stalled = sctl[2] >= 40;
-    for (int k = 1 + tid; k <= hh; k += NT) {
-      const double hk = fabs(HH(k, k - 1));
-      bool small = hk <= kSafeMin || (stalled && hk <= kUlp * hnorm);
-      if (!small) {
-        double tst = fabs(HH(k - 1, k - 1)) + fabs(HH(k, k));
-        if (tst == 0.0) {
-          if (k >= 2) tst += fabs(HH(k - 1, k - 2));
-          if (k + 1 <= hh) tst += fabs(HH(k + 1, k));
-        }
-        if (hk <= kUlp * tst) {
-          const double hu = fabs(HH(k - 1, k));
-          const double ab = fmax(hk, hu), ba = fmin(hk, hu);
-          const double dd = fabs(HH(k - 1, k - 1) - HH(k, k));
-          const double aa = fmax(fabs(HH(k, k)), dd), bb = fmin(fabs(HH(k, k)), dd);
-          const double s = aa + ab;
-          small = ba * (ab / s) <= fmax(kSafeMin, kUlp * (bb * (aa / s)));
-        }
-      }
-      if (small) cand = max(cand, k);
-    }
-    const int l = block_max(cand, sredi);
-    if (tid == 0) {
-      if (l > 0) HH(l, l - 1) = 0.0;
-      if (l == hh) {  // 1x1 block
-        lre[hh] = HH(hh, hh);
-        lim[hh] = 0.0;
-        blk[hh] = 1;
-        sctl[1] = hh - 1;
-        sctl[2] = 0;
-        sctl[4] = 0;
-      } else if (l == hh - 1) {  // 2x2 block
-        const double a = HH(hh - 1, hh - 1), b = HH(hh - 1, hh), c = HH(hh, hh - 1), d = HH(hh, hh);
-        const double p = 0.5 * (a - d), bc = b * c, disc = p * p + bc;
-        if (disc >= 0.0) {
-          // real pair: rotate the block to upper triangular form (first column = eigenvector of
-          // the first eigenvalue) so that both become 1x1 blocks; applied by all threads below
-          const double zz = p + copysign(sqrt(disc), p);
-          const double l1 = d + zz;
-          double v0 = b, v1 = l1 - a;
-          const double w0 = l1 - d, w1 = c;
-          if (fabs(w0) + fabs(w1) > fabs(v0) + fabs(v1)) {
-            v0 = w0;
-            v1 = w1;
-          }
-          const double nv = hypot(v0, v1);
-          sxyz[0] = (nv > 0.0) ? v0 / nv : 1.0;
-          sxyz[1] = (nv > 0.0) ? v1 / nv : 0.0;
-          sctl[4] = 2;
-        } else {
-          lre[hh - 1] = lre[hh] = 0.5 * (a + d);
-          lim[hh - 1] = sqrt(-disc);
-          lim[hh] = -sqrt(-disc);
-          blk[hh - 1] = 2;
-          blk[hh] = 0;
-          sctl[1] = hh - 2;
-          sctl[2] = 0;
-          sctl[4] = 0;
-        }
+    if (wave0) {
+      const int hh = sctl[1];
+      if (hh < 0) {
+        if (lane == 0) sctl[4] = kActStop;
       } else {
-        const int its = ++sctl[2];
-        const int tot = ++sctl[3];
-        if (its > 100 || tot > 60 * n) {
-          sctl[5] = 1;
-          sctl[4] = 0;
-          sctl[1] = -1;
-        } else {
-          double h11, h12, h21, h22;
-          if (its % 20 == 10) {
-            const double s = fabs(HH(l + 1, l)) + fabs(HH(l + 2, l + 1));
-            h11 = 0.75 * s + HH(l, l);
-            h12 = -0.4375 * s;
-            h21 = s;
-            h22 = h11;
-          } else if (its % 20 == 0) {
-            const double s = fabs(HH(hh, hh - 1)) + fabs(HH(hh - 1, hh - 2));
-            h11 = 0.75 * s + HH(hh, hh);
-            h12 = -0.4375 * s;
-            h21 = s;
-            h22 = h11;
-          } else {
-            h11 = HH(hh - 1, hh - 1);
-            h12 = HH(hh - 1, hh);
-            h21 = HH(hh, hh - 1);
-            h22 = HH(hh, hh);
-          }
-          // shifts = eigenvalues of [[h11, h12], [h21, h22]]; a real pair is replaced by the root
-          // closer to h22 used twice (keeps the iteration from stagnating on real clusters)
-          double s1r, s1i, s2r, s2i;
-          {
-            const double hp = 0.5 * (h11 - h22), bc = h12 * h21, disc = hp * hp + bc;
-            if (disc >= 0.0) {
-              const double zz = hp + copysign(sqrt(disc), hp);
-              const double d1 = zz, d2 = (zz != 0.0) ? -bc / zz : 0.0;  // root - h22
-              const double rt = h22 + ((fabs(d1) <= fabs(d2)) ? d1 : d2);
-              s1r = s2r = rt;
-              s1i = s2i = 0.0;
-            } else {
-              s1r = s2r = h22 + hp;
-              s1i = sqrt(-disc);
-              s2i = -s1i;
+        int cand = 0;
+        for (int k = 1 + lane; k <= hh; k += W0) {
+          const double hk = fabs(HH(k, k - 1));
+          bool small = hk <= kSafeMin || (sctl[2] >= 40 && hk <= kUlp * hnorm);
+          if (!small) {
+            double tst = fabs(HH(k - 1, k - 1)) + fabs(HH(k, k));
+            if (tst == 0.0) {
+              if (k >= 2) tst += fabs(HH(k - 1, k - 2));
+              if (k + 1 <= hh) tst += fabs(HH(k + 1, k));
+            }
+            if (hk <= kUlp * tst) {
+              const double hu = fabs(HH(k - 1, k));
+              const double ab = fmax(hk, hu), ba = fmin(hk, hu);
+              const double dd = fabs(HH(k - 1, k - 1) - HH(k, k));
+              const double aa = fmax(fabs(HH(k, k)), dd), bb = fmin(fabs(HH(k, k)), dd);
+              const double s = aa + ab;
+              small = ba * (ab / s) <= fmax(kSafeMin, kUlp * (bb * (aa / s)));
             }
           }
-          // first column of (H - s1)(H - s2) at row l, in product form (no cancellation)
-          const double a0 = HH(l, l), a1 = HH(l + 1, l);
-          const double sc = fabs(a0 - s2r) + fabs(s2i) + fabs(a1);
-          const double a1s = a1 / sc;
-          sxyz[0] = a1s * HH(l, l + 1) + (a0 - s1r) * ((a0 - s2r) / sc) - s1i * (s2i / sc);
-          sxyz[1] = a1s * (a0 + HH(l + 1, l + 1) - s1r - s2r);
-          sxyz[2] = a1s * HH(l + 2, l + 1);
-          sctl[6] = l;
-          sctl[4] = 1;  // sweep
+          if (small) cand = max(cand, k);
+        }
+        const int l = wave_max(cand);
+        if (lane == 0) {
+          if (l > 0) HH(l, l - 1) = 0.0;
+          if (l == hh) {  // 1x1 block
+            lre[hh] = HH(hh, hh);
+            lim[hh] = 0.0;
+            blk[hh] = 1;
+            sctl[1] = hh - 1;
+            sctl[2] = 0;
+            sctl[4] = kActDeflated;
+          } else if (l == hh - 1) {  // 2x2 block
+            const double a = HH(hh - 1, hh - 1), b = HH(hh - 1, hh), c = HH(hh, hh - 1), d = HH(hh, hh);
+            const double p = 0.5 * (a - d), bc = b * c, disc = p * p + bc;
+            if (disc >= 0.0) {
+              // real pair: rotate the block to upper triangular form (first column = eigenvector
+              // of the first eigenvalue) so that both become 1x1 blocks
+              const double zz = p + copysign(sqrt(disc), p);
+              const double l1 = d + zz;
+              double v0 = b, v1 = l1 - a;
+              const double w0 = l1 - d, w1 = c;
+              if (fabs(w0) + fabs(w1) > fabs(v0) + fabs(v1)) {
+                v0 = w0;
+                v1 = w1;
+              }
+              const double nv = hypot(v0, v1);
+              sxyz[0] = (nv > 0.0) ? v0 / nv : 1.0;
+              sxyz[1] = (nv > 0.0) ? v1 / nv : 0.0;
+              sctl[0] = hh;
+              sctl[4] = kActRotate;
+            } else {
+              lre[hh - 1] = lre[hh] = 0.5 * (a + d);
+              lim[hh - 1] = sqrt(-disc);
+              lim[hh] = -sqrt(-disc);
+              blk[hh - 1] = 2;
+              blk[hh] = 0;
+              sctl[1] = hh - 2;
+              sctl[2] = 0;
+              sctl[4] = kActDeflated;
+            }
+          } else {
+            const int its = ++sctl[2];
+            const int tot = ++sctl[3];
+            if (its > 100 || tot > 60 * n) {
+              sctl[5] = 1;
+              sctl[1] = -1;
+              sctl[4] = kActStop;
+            } else {
+              double h11, h12, h21, h22;
+              if (its % 20 == 10) {
+                const double s = fabs(HH(l + 1, l)) + fabs(HH(l + 2, l + 1));
+                h11 = 0.75 * s + HH(l, l);
+                h12 = -0.4375 * s;
+                h21 = s;
+                h22 = h11;
+              } else if (its % 20 == 0) {
+                const double s = fabs(HH(hh, hh - 1)) + fabs(HH(hh - 1, hh - 2));
+                h11 = 0.75 * s + HH(hh, hh);
+                h12 = -0.4375 * s;
+                h21 = s;
+                h22 = h11;
+              } else {
+                h11 = HH(hh - 1, hh - 1);
+                h12 = HH(hh - 1, hh);
+                h21 = HH(hh, hh - 1);
+                h22 = HH(hh, hh);
+              }
+              // shifts = eigenvalues of [[h11, h12], [h21, h22]]; a real pair is replaced by the
+              // root closer to h22 used twice (keeps the iteration from stagnating on real clusters)
+              double s1r, s1i, s2r, s2i;
+              {
+                const double hp = 0.5 * (h11 - h22), bc = h12 * h21, disc = hp * hp + bc;
+                if (disc >= 0.0) {
+                  const double zz = hp + copysign(sqrt(disc), hp);
+                  const double d1 = zz, d2 = (zz != 0.0) ? -bc / zz : 0.0;  // root - h22
+                  const double rt = h22 + ((fabs(d1) <= fabs(d2)) ? d1 : d2);
+                  s1r = s2r = rt;
+                  s1i = s2i = 0.0;
+                } else {
+                  s1r = s2r = h22 + hp;
+                  s1i = sqrt(-disc);
+                  s2i = -s1i;
+                }
+              }
+              // first column of (H - s1)(H - s2) at row l, in product form (no cancellation)
+              const double a0 = HH(l, l), a1 = HH(l + 1, l);
+              const double sc = fabs(a0 - s2r) + fabs(s2i) + fabs(a1);
+              const double a1s = a1 / sc;
+              sxyz[0] = a1s * HH(l, l + 1) + (a0 - s1r) * ((a0 - s2r) / sc) - s1i * (s2i / sc);
+              sxyz[1] = a1s * (a0 + HH(l + 1, l + 1) - s1r - s2r);
+              sxyz[2] = a1s * HH(l + 2, l + 1);
+              sctl[6] = l;
+              sctl[0] = hh;
+              sctl[4] = kActSweep;
+            }
+          }
+        }
+        wave_sync();
+        if (sctl[4] == kActSweep) {
+          // bulge chase over rows/columns lo..hh by wave 0
+          const int lo = sctl[6];
+          for (int k = lo; k <= hh - 1; ++k) {
+            const bool three = k < hh - 1;
+            double x, y, z;
+            if (k == lo) {
+              x = sxyz[0];
+              y = sxyz[1];
+              z = sxyz[2];
+            } else {
+              x = HH(k, k - 1);
+              y = HH(k + 1, k - 1);
+              z = three ? HH(k + 2, k - 1) : 0.0;
+            }
+            if (!three) z = 0.0;
+            const double nrm = sqrt(x * x + y * y + z * z);
+            double tau = 0.0, u1 = 0.0, u2 = 0.0, beta = 0.0;
+            if (nrm != 0.0 && (y != 0.0 || z != 0.0)) {
+              beta = (x >= 0.0) ? -nrm : nrm;
+              tau = (beta - x) / beta;
+              const double sc = 1.0 / (x - beta);
+              u1 = y * sc;
+              u2 = z * sc;
+            }
+            wave_sync();  // every lane has read column k - 1 before lane 0 overwrites it
+            if (lane == 0) {
+              srefl[3 * k] = tau;
+              srefl[3 * k + 1] = u1;
+              srefl[3 * k + 2] = u2;
+            }
+            if (tau != 0.0) {
+              if (lane == 0 && k > lo) {
+                HH(k, k - 1) = beta;
+                HH(k + 1, k - 1) = 0.0;
+                if (three) HH(k + 2, k - 1) = 0.0;
+              }
+              for (int c = k + lane; c < n; c += W0) {  // rows k..k+2, columns right of k-1
+                if (three) {
+                  const double w = tau * (HH(k, c) + u1 * HH(k + 1, c) + u2 * HH(k + 2, c));
+                  HH(k, c) -= w;
+                  HH(k + 1, c) -= w * u1;
+                  HH(k + 2, c) -= w * u2;
+                } else {
+                  const double w = tau * (HH(k, c) + u1 * HH(k + 1, c));
+                  HH(k, c) -= w;
+                  HH(k + 1, c) -= w * u1;
+                }
+              }
+              wave_sync();
+              const int rmax = min(k + 3, hh);
+              for (int r = lane; r <= rmax; r += W0) {  // columns k..k+2, rows 0..k+3
+                if (three) {
+                  const double w = tau * (HH(r, k) + u1 * HH(r, k + 1) + u2 * HH(r, k + 2));
+                  HH(r, k) -= w;
+                  HH(r, k + 1) -= w * u1;
+                  HH(r, k + 2) -= w * u2;
+                } else {
+                  const double w = tau * (HH(r, k) + u1 * HH(r, k + 1));
+                  HH(r, k) -= w;
+                  HH(r, k + 1) -= w * u1;
+                }
+              }
+              wave_sync();
+            }
+          }
         }
       }
     }
     __syncthreads();
-    if (sctl[4] == 0) continue;  // deflated (or failed: hh < 0 ends the loop)
-    if (sctl[4] == 2) {          // split a real 2x2 block with the rotation [[cs, -sn], [sn, cs]]
+    const int act = sctl[4];
+    if (act == kActStop) break;
+    if (act == kActSweep) {
+      // delayed application of the sweep's reflectors to the rows of Z
+      const int lo = sctl[6], hh = sctl[0];
+      for (int r = tid; r < n; r += NT) {
+        double z0 = ZZ(r, lo), z1 = ZZ(r, lo + 1);
+        for (int k = lo; k <= hh - 1; ++k) {
+          const bool three = k < hh - 1;
+          double z2 = three ? ZZ(r, k + 2) : 0.0;
+          const double tau = srefl[3 * k];
+          if (tau != 0.0) {
+            const double u1 = srefl[3 * k + 1], u2 = srefl[3 * k + 2];
+            const double w = tau * (z0 + u1 * z1 + (three ? u2 * z2 : 0.0));
+            z0 -= w;
+            z1 -= w * u1;
+            if (three) z2 -= w * u2;
+          }
+          ZZ(r, k) = z0;
+          z0 = z1;
+          z1 = z2;
+        }
+        ZZ(r, hh) = z0;
+      }
+    } else if (act == kActRotate) {  // split a real 2x2 block with [[cs, -sn], [sn, cs]]
+      const int hh = sctl[0], h1 = hh - 1;
       const double cs = sxyz[0], sn = sxyz[1];
-      const int h1 = hh - 1;
       for (int c = h1 + tid; c < n; c += NT) {
         const double x = HH(h1, c), y = HH(hh, c);
         HH(h1, c) = cs * x + sn * y;
@@ -343,94 +444,6 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
         sctl[1] = hh - 2;
         sctl[2] = 0;
       }
-      __syncthreads();
-      continue;
-    }
-
-    const int lo = sctl[6];
-    for (int k = lo; k <= hh - 1; ++k) {
-      const bool three = k < hh - 1;
-      if (tid == 0) {
-        double x, y, z;
-        if (k == lo) {
-          x = sxyz[0];
-          y = sxyz[1];
-          z = sxyz[2];
-        } else {
-          x = HH(k, k - 1);
-          y = HH(k + 1, k - 1);
-          z = three ? HH(k + 2, k - 1) : 0.0;
-        }
-        if (!three) z = 0.0;
-        const double nrm = sqrt(x * x + y * y + z * z);
-        double tau = 0.0, u1 = 0.0, u2 = 0.0;
-        if (nrm != 0.0 && (y != 0.0 || z != 0.0)) {
-          const double beta = (x >= 0.0) ? -nrm : nrm;
-          tau = (beta - x) / beta;
-          const double sc = 1.0 / (x - beta);
-          u1 = y * sc;
-          u2 = z * sc;
-          if (k > lo) {
-            HH(k, k - 1) = beta;
-            HH(k + 1, k - 1) = 0.0;
-            if (three) HH(k + 2, k - 1) = 0.0;
-          }
-        }
-        srefl[3 * k] = tau;
-        srefl[3 * k + 1] = u1;
-        srefl[3 * k + 2] = u2;
-      }
-      __syncthreads();
-      const double tau = srefl[3 * k], u1 = srefl[3 * k + 1], u2 = srefl[3 * k + 2];
-      if (tau != 0.0) {
-        for (int c = k + tid; c < n; c += NT) {  // rows k..k+2, all columns right of k-1
-          if (three) {
-            const double w = tau * (HH(k, c) + u1 * HH(k + 1, c) + u2 * HH(k + 2, c));
-            HH(k, c) -= w;
-            HH(k + 1, c) -= w * u1;
-            HH(k + 2, c) -= w * u2;
-          } else {
-            const double w = tau * (HH(k, c) + u1 * HH(k + 1, c));
-            HH(k, c) -= w;
-            HH(k + 1, c) -= w * u1;
-          }
-        }
-        __syncthreads();
-        const int rmax = min(k + 3, hh);
-        for (int r = tid; r <= rmax; r += NT) {  // columns k..k+2, rows 0..k+3
-          if (three) {
-            const double w = tau * (HH(r, k) + u1 * HH(r, k + 1) + u2 * HH(r, k + 2));
-            HH(r, k) -= w;
-            HH(r, k + 1) -= w * u1;
-            HH(r, k + 2) -= w * u2;
-          } else {
-            const double w = tau * (HH(r, k) + u1 * HH(r, k + 1));
-            HH(r, k) -= w;
-            HH(r, k + 1) -= w * u1;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    // delayed application of the sweep's reflectors to the rows of Z
-    for (int r = tid; r < n; r += NT) {
-      double z0 = ZZ(r, lo), z1 = ZZ(r, lo + 1);
-      for (int k = lo; k <= hh - 1; ++k) {
-        const bool three = k < hh - 1;
-        double z2 = three ? ZZ(r, k + 2) : 0.0;
-        const double tau = srefl[3 * k];
-        if (tau != 0.0) {
-          const double u1 = srefl[3 * k + 1], u2 = srefl[3 * k + 2];
-          const double w = tau * (z0 + u1 * z1 + (three ? u2 * z2 : 0.0));
-          z0 -= w;
-          z1 -= w * u1;
-          if (three) z2 -= w * u2;
-        }
-        ZZ(r, k) = z0;
-        z0 = z1;
-        z1 = z2;
-      }
-      ZZ(r, hh) = z0;
     }
     __syncthreads();
   }
@@ -446,11 +459,12 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
     const int b0 = (blk[j] == 0) ? j - 1 : j;   // own block start
     const int bend = (blk[b0] == 2) ? b0 + 1 : b0;
     const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
-    // Eigenvalues closer than a few ulp ||G|| cannot be told apart: a diagonal entry (or 2x2 block)
-    // that close to lambda is another copy of the same multiple eigenvalue of a diagonalisable
-    // matrix (e.g. the unscattered Stokes components at one node, lambda = 1/mu^2), and its Schur
-    // coupling is rounding noise. Its component is set to zero instead of dividing the noise by a
-    // guarded pivot, which would make the copies' eigenvectors parallel.
+    // Eigenvalues closer than a few ulp ||G|| cannot be told apart: a diagonal entry (or 2x2
+    // block) that close to lambda is another copy of the same multiple eigenvalue of a
+    // diagonalisable matrix (e.g. the unscattered Stokes components at one node,
+    // lambda = 1/mu^2), and its Schur coupling is rounding noise. Its component is set to zero
+    // instead of dividing the noise by a guarded pivot, which would make the copies' eigenvectors
+    // parallel.
     const double same = 8.0 * kUlp * hnorm;
     const bool cplx = wi > 0.0;
     const Cx lam{wr, wi};
@@ -488,16 +502,33 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
     while (i >= 0) {
       const int s = (blk[i] == 0) ? i - 1 : i;  // block [s, i]
       Cx r0{0.0, 0.0}, r1{0.0, 0.0};
-      for (int c = i + 1; c <= bend; ++c) {
-        const Cx xc{XT[(int64_t)c * n + j], cplx ? XT[(int64_t)c * n + j + 1] : 0.0};
-        const double t0 = HH(s, c);
-        r0.re -= t0 * xc.re;
-        r0.im -= t0 * xc.im;
-        if (s < i) {
-          const double t1 = HH(i, c);
-          r1.re -= t1 * xc.re;
-          r1.im -= t1 * xc.im;
+      if (cplx) {
+        for (int c = i + 1; c <= bend; ++c) {
+          const double xr = XT[(int64_t)c * n + j], xi = XT[(int64_t)c * n + j + 1];
+          const double t0 = HH(s, c);
+          r0.re -= t0 * xr;
+          r0.im -= t0 * xi;
+          if (s < i) {
+            const double t1 = HH(i, c);
+            r1.re -= t1 * xr;
+            r1.im -= t1 * xi;
+          }
         }
+      } else if (s == i) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int c = i + 1; c <= bend; ++c) acc -= HH(s, c) * XT[(int64_t)c * n + j];
+        r0.re = acc;
+      } else {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll 4
+        for (int c = i + 1; c <= bend; ++c) {
+          const double xc = XT[(int64_t)c * n + j];
+          a0 -= HH(s, c) * xc;
+          a1 -= HH(i, c) * xc;
+        }
+        r0.re = a0;
+        r1.re = a1;
       }
       if (s == i) {
         const Cx d0 = csub(Cx{HH(i, i), 0.0}, lam);
@@ -539,6 +570,23 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
   }
 #undef HH
 #undef ZZ
+}
+
+__global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, int32_t* status) {
+  const Item it = items[blockIdx.x];
+  if (status[it.layer] != 0) return;
+  __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1)];
+  __shared__ double sv[kMaxn];
+  __shared__ double srefl[3 * kMaxn];
+  __shared__ double sred[8];
+  __shared__ int sredi[8];
+  __shared__ int sctl[8];
+  __shared__ double sxyz[3];
+  double* base = ws + it.ws;
+  if (it.n <= kLdsMaxn)
+    eigen_body<true>(it, base, status, sH, sv, srefl, sred, sredi, sctl, sxyz);
+  else
+    eigen_body<false>(it, base, status, sH, sv, srefl, sred, sredi, sctl, sxyz);
 }
 
 }  // namespace vbrdf
