@@ -102,9 +102,66 @@ __device__ __forceinline__ void wave_sync() {
 // Action codes of the QR driver (sctl[4]).
 enum : int { kActDeflated = 0, kActSweep = 1, kActRotate = 2, kActStop = 3 };
 
+// Z-update descriptor of one QR iteration, produced by wave 0 and applied by the other waves
+// during the next iteration (double-buffered): kind 0 none, 1 sweep (reflectors of steps lo..hh-1
+// as (tau, u1, u2) triples in the slot's reflector buffer), 2 rotation of columns hh-1, hh by
+// (cs, sn) stored at the start of the reflector buffer. `stop` ends the QR loop after this
+// iteration; it lives in the double-buffered slot so that wave 0 cannot overwrite it (in the
+// next iteration) before every wave has read it.
+struct ZOp {
+  int kind, lo, hh, stop;
+};
+
+// Applies one ZOp to rows t0, t0 + nt, ... of Z (Z(r, c) at ZT[c * n + r]).
+__device__ __forceinline__ void apply_zop(const ZOp& op, const double* rf, double* __restrict__ ZT, int n, int t0,
+                                          int nt) {
+  if (op.kind == 1) {
+    const int lo = op.lo, hh = op.hh;
+    for (int r = t0; r < n; r += nt) {
+      double z0 = ZT[(int64_t)lo * n + r], z1 = ZT[(int64_t)(lo + 1) * n + r];
+      for (int k0 = lo; k0 <= hh - 1; k0 += 8) {
+        double zb[8];  // window entries of the next 8 steps, loaded ahead (not yet written)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int c = k0 + 2 + j;
+          zb[j] = (c <= hh) ? ZT[(int64_t)c * n + r] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int k = k0 + j;
+          if (k <= hh - 1) {
+            const bool three = k < hh - 1;
+            double z2 = three ? zb[j] : 0.0;
+            const double tau = rf[3 * k];
+            if (tau != 0.0) {
+              const double u1 = rf[3 * k + 1], u2 = rf[3 * k + 2];
+              const double w = tau * (z0 + u1 * z1 + (three ? u2 * z2 : 0.0));
+              z0 -= w;
+              z1 -= w * u1;
+              if (three) z2 -= w * u2;
+            }
+            ZT[(int64_t)k * n + r] = z0;
+            z0 = z1;
+            z1 = z2;
+          }
+        }
+      }
+      ZT[(int64_t)hh * n + r] = z0;
+    }
+  } else if (op.kind == 2) {
+    const int h1 = op.hh - 1, hh = op.hh;
+    const double cs = rf[0], sn = rf[1];
+    for (int r = t0; r < n; r += nt) {
+      const double zx = ZT[(int64_t)h1 * n + r], zy = ZT[(int64_t)hh * n + r];
+      ZT[(int64_t)h1 * n + r] = cs * zx + sn * zy;
+      ZT[(int64_t)hh * n + r] = -sn * zx + cs * zy;
+    }
+  }
+}
+
 template <bool kLds>
-__device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t* status, double* sH, double* sv,
-                                           double* srefl, double* sred, int* sredi, int* sctl, double* sxyz) {
+__device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t* status, double* sH, double* srefl,
+                                           double* sred, int* sctl, double* sxyz, ZOp* zops) {
   const int n = it.n;
   double* G = base + (int64_t)kBufG * n * n;
   double* __restrict__ ZT = base + (int64_t)kBufZ * n * n;  // Z(r, c) = ZT[c * n + r]
@@ -118,8 +175,11 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
   const bool wave0 = tid < 64;
   const int W0 = NT < 64 ? NT : 64;  // lanes of wave 0
   double* H = kLds ? sH : G;
-  const int64_t ld = kLds ? n + 1 : n;
-#define HH(r, c) H[(int64_t)(r) * ld + (c)]
+  // In LDS the row stride is the fixed kLdsMaxn + 1 (offsets become immediates); the rows
+  // beyond the matrix and a tail of 3 doubles per lane absorb loads and stores of idle lanes.
+  const int64_t ld = kLds ? kLdsMaxn + 1 : n;
+  double* sv = srefl;  // Householder vector of the reduction (the reflector buffers are free then)
+#define HH(r, c) H[(kLds ? (int64_t)(int)((r) * (int)ld + (c)) : (int64_t)(r) * ld + (c))]
 #define ZZ(r, c) ZT[(int64_t)(c) * n + (r)]
 
   // ---- load, Z = I
@@ -143,7 +203,11 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
   const double hnorm = sxyz[0];
   __syncthreads();
 
-  // ---- 1. Householder reduction to Hessenberg form, Z accumulated
+  // ---- 1. Householder reduction to Hessenberg form, Z accumulated. Each dot product of the
+  // two-sided update is split over P adjacent lanes (combined by lane exchange) so that all
+  // threads work although a step has at most n columns and n rows.
+  int Pr = 1;
+  while (Pr < 4 && n * Pr * 2 <= NT) Pr *= 2;
   for (int k = 0; k + 2 < n; ++k) {
     double part = 0.0;
     for (int i = k + 2 + tid; i < n; i += NT) part += HH(i, k) * HH(i, k);
@@ -158,48 +222,75 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     for (int i = tid; i < len; i += NT) sv[i] = (i == 0) ? 1.0 : HH(k + 1 + i, k) * scal;
     __syncthreads();
     for (int i = tid; i < len; i += NT) HH(k + 1 + i, k) = (i == 0) ? beta : 0.0;
-    for (int c = k + 1 + tid; c < n; c += NT) {  // left: (I - tau v v^T) H
+    // left: (I - tau v v^T) H on columns k+1..n-1
+    int Pl = 1;
+    while (Pl < 8 && len * Pl * 2 <= NT) Pl *= 2;
+    const int part_l = tid & (Pl - 1);
+    for (int c0 = k + 1; c0 < n; c0 += NT / Pl) {
+      const int c = c0 + tid / Pl;
       double w = 0.0;
-#pragma unroll 8
-      for (int i = 0; i < len; ++i) w += sv[i] * HH(k + 1 + i, c);
+      if (c < n) {
+#pragma unroll 4
+        for (int i = part_l; i < len; i += Pl) w += sv[i] * HH(k + 1 + i, c);
+      }
+      for (int o = 1; o < Pl; o <<= 1) w += __shfl_xor(w, o);
       w *= tau;
-#pragma unroll 8
-      for (int i = 0; i < len; ++i) HH(k + 1 + i, c) -= sv[i] * w;
+      if (c < n) {
+#pragma unroll 4
+        for (int i = part_l; i < len; i += Pl) HH(k + 1 + i, c) -= sv[i] * w;
+      }
     }
     __syncthreads();
-    for (int r = tid; r < n; r += NT) {  // right: H (I - tau v v^T), and Z likewise
-      double y = 0.0;
-#pragma unroll 8
-      for (int i = 0; i < len; ++i) y += HH(r, k + 1 + i) * sv[i];
+    // right: H (I - tau v v^T) and Z likewise, rows 0..n-1
+    const int part_r = tid & (Pr - 1);
+    for (int r0 = 0; r0 < n; r0 += NT / Pr) {
+      const int r = r0 + tid / Pr;
+      double y = 0.0, yz = 0.0;
+      if (r < n) {
+#pragma unroll 4
+        for (int i = part_r; i < len; i += Pr) {
+          y += HH(r, k + 1 + i) * sv[i];
+          yz += ZZ(r, k + 1 + i) * sv[i];
+        }
+      }
+      for (int o = 1; o < Pr; o <<= 1) {
+        y += __shfl_xor(y, o);
+        yz += __shfl_xor(yz, o);
+      }
       y *= tau;
-#pragma unroll 8
-      for (int i = 0; i < len; ++i) HH(r, k + 1 + i) -= y * sv[i];
-      double yz = 0.0;
-#pragma unroll 8
-      for (int i = 0; i < len; ++i) yz += ZZ(r, k + 1 + i) * sv[i];
       yz *= tau;
-#pragma unroll 8
-      for (int i = 0; i < len; ++i) ZZ(r, k + 1 + i) -= yz * sv[i];
+      if (r < n) {
+#pragma unroll 4
+        for (int i = part_r; i < len; i += Pr) {
+          HH(r, k + 1 + i) -= y * sv[i];
+          ZZ(r, k + 1 + i) -= yz * sv[i];
+        }
+      }
     }
     __syncthreads();
   }
 
   // ---- 2. Francis double-shift QR to real Schur form
-  // Wave 0 runs the deflation scan, the shift choice and each sweep's bulge chase on its own
-  // (lane-synchronous, no workgroup barrier inside a sweep; every lane computes the reflector);
-  // all waves then apply the sweep's reflectors to Z.
+  // Wave 0 runs the deflation scan, the shift choice, each sweep's bulge chase and the block
+  // splitting on its own (lane-synchronous, no workgroup barrier inside an iteration). The
+  // orthogonal factor is updated one iteration behind by the other waves, from the reflectors
+  // wave 0 left in LDS, so the two overlap. With a single wave the update follows at once.
+  const bool split = NT > 64;
   if (tid == 0) {
     sctl[1] = n - 1;  // active bottom index hh
     sctl[2] = 0;      // iterations since last deflation
     sctl[3] = 0;      // total iterations
     sctl[5] = 0;      // failure flag
+    zops[0] = zops[1] = ZOp{0, 0, 0, 0};
   }
   __syncthreads();
-  while (true) {
+  for (int iter = 0;; ++iter) {
+    const int slot = iter & 1;
+    double* rf = srefl + slot * 3 * kMaxn;
     if (wave0) {
-      const int hh = sctl[1];
+      const int hh = __builtin_amdgcn_readfirstlane(sctl[1]);
       if (hh < 0) {
-        if (lane == 0) sctl[4] = kActStop;
+        if (lane == 0) zops[slot] = ZOp{0, 0, 0, 1};
       } else {
         int cand = 0;
         for (int k = 1 + lane; k <= hh; k += W0) {
@@ -224,6 +315,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
         }
         const int l = wave_max(cand);
         if (lane == 0) {
+          zops[slot] = ZOp{0, 0, 0, 0};
           if (l > 0) HH(l, l - 1) = 0.0;
           if (l == hh) {  // 1x1 block
             lre[hh] = HH(hh, hh);
@@ -249,7 +341,6 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               const double nv = hypot(v0, v1);
               sxyz[0] = (nv > 0.0) ? v0 / nv : 1.0;
               sxyz[1] = (nv > 0.0) ? v1 / nv : 0.0;
-              sctl[0] = hh;
               sctl[4] = kActRotate;
             } else {
               lre[hh - 1] = lre[hh] = 0.5 * (a + d);
@@ -268,6 +359,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               sctl[5] = 1;
               sctl[1] = -1;
               sctl[4] = kActStop;
+              zops[slot].stop = 1;
             } else {
               double h11, h12, h21, h22;
               if (its % 20 == 10) {
@@ -313,139 +405,345 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               sxyz[1] = a1s * (a0 + HH(l + 1, l + 1) - s1r - s2r);
               sxyz[2] = a1s * HH(l + 2, l + 1);
               sctl[6] = l;
-              sctl[0] = hh;
               sctl[4] = kActSweep;
             }
           }
         }
         wave_sync();
-        if (sctl[4] == kActSweep) {
-          // bulge chase over rows/columns lo..hh by wave 0
-          const int lo = sctl[6];
-          for (int k = lo; k <= hh - 1; ++k) {
-            const bool three = k < hh - 1;
-            double x, y, z;
-            if (k == lo) {
-              x = sxyz[0];
-              y = sxyz[1];
-              z = sxyz[2];
-            } else {
-              x = HH(k, k - 1);
-              y = HH(k + 1, k - 1);
-              z = three ? HH(k + 2, k - 1) : 0.0;
+        const int act = __builtin_amdgcn_readfirstlane(sctl[4]);
+        if (act == kActSweep) {
+          // Bulge chase over rows/columns lo..hh. A three-element step k touches rows k..k+2
+          // (columns >= k) and columns k..k+2 (rows <= k+3); every lane loads the 4 x 3 corner
+          // block those share, updates it itself (left, then right) and so holds the next
+          // step's reflector input, column k rows k+1..k+3, in registers. The loads of a step
+          // are issued before its reflector is formed.
+          const int lo = __builtin_amdgcn_readfirstlane(sctl[6]);
+          double x = sxyz[0], y = sxyz[1], z = sxyz[2];
+          if constexpr (kLds) {
+            // Off-block work as n - 3 uniform jobs of three elements each: job j < n - k - 3 is
+            // column k + 3 + j (rows k..k+2, left update), the rest are rows 0..k-1 (columns
+            // k..k+2, right update). Relative to the block origin k (ld + 1) a job starts at
+            // 3 + j (stride ld) or at (j - n + 3) ld (stride 1). Each lane owns jobs lane and
+            // lane + 64; an idle slot works on its private triple in the LDS tail.
+            constexpr int LD = kLdsMaxn + 1;
+            const int ja = lane, jb = lane + W0;
+            const int dum = kLdsMaxn * LD + 3 * lane;
+            for (int k = lo; k < hh - 1; ++k) {
+              const int kb = k * (LD + 1);
+              double b[4][3];  // rows k..k+3, columns k..k+2 (row k+3 is unused when k+3 > hh)
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) b[i][j] = H[kb + i * LD + j];
+              const bool cola = k < n - 3 - ja, colb = k < n - 3 - jb;
+              int ia = cola ? kb + 3 + ja : kb + (ja - n + 3) * LD, sa = cola ? LD : 1;
+              int ib = colb ? kb + 3 + jb : kb + (jb - n + 3) * LD, sb = colb ? LD : 1;
+              if (ja >= n - 3) {
+                ia = dum;
+                sa = 1;
+              }
+              if (jb >= n - 3) {
+                ib = dum;
+                sb = 1;
+              }
+              double va[3], vb[3];
+#pragma unroll
+              for (int i = 0; i < 3; ++i) {
+                va[i] = H[ia + i * sa];
+                vb[i] = H[ib + i * sb];
+              }
+              wave_sync();  // all loads of the step precede its stores
+              // Reflector (I - tau u u^T), u = (1, u1, u2), taking (x, y, z) to (beta, 0, 0)
+              // with beta = -sign(x) ||(x, y, z)||. Then tau = 1 + |x| / ||.|| and
+              // 1 / (x - beta) = sign(x) / (|x| + ||.||): one reciprocal square root and one
+              // reciprocal, each refined by two Newton steps. With y = z = 0 the step is the
+              // identity (tau = 0, beta = x) and the updates below rewrite the same values.
+              double tau = 0.0, u1 = 0.0, u2 = 0.0, beta = x;
+              if (y != 0.0 || z != 0.0) {
+                double xs = x, ys = y, zs = z, unscale = 1.0;
+                double s2 = xs * xs + ys * ys + zs * zs;
+                if (s2 < 0x1p-900) {  // keep the squares clear of the subnormal range
+                  xs *= 0x1p600;
+                  ys *= 0x1p600;
+                  zs *= 0x1p600;
+                  unscale = 0x1p-600;
+                  s2 = xs * xs + ys * ys + zs * zs;
+                }
+                double r = __builtin_amdgcn_rsq(s2);
+                const double h2 = 0.5 * s2;
+                r = r * fma(-h2 * r, r, 1.5);
+                r = r * fma(-h2 * r, r, 1.5);
+                const double nrm = s2 * r;
+                const double ax = fabs(xs);
+                tau = fma(ax, r, 1.0);
+                const double dd = ax + nrm;
+                double q = __builtin_amdgcn_rcp(dd);
+                q = fma(q, fma(-dd, q, 1.0), q);
+                q = fma(q, fma(-dd, q, 1.0), q);
+                const double sc = copysign(q, xs);
+                u1 = ys * sc;
+                u2 = zs * sc;
+                beta = -copysign(nrm, xs) * unscale;
+              }
+              {
+                const double w = tau * (va[0] + u1 * va[1] + u2 * va[2]);
+                H[ia] = va[0] - w;
+                H[ia + sa] = va[1] - w * u1;
+                H[ia + 2 * sa] = va[2] - w * u2;
+              }
+              {
+                const double w = tau * (vb[0] + u1 * vb[1] + u2 * vb[2]);
+                H[ib] = vb[0] - w;
+                H[ib + sb] = vb[1] - w * u1;
+                H[ib + 2 * sb] = vb[2] - w * u2;
+              }
+              for (int j = lane + 2 * W0; j < n - 3; j += W0) {  // only with fewer than 64 lanes
+                const int jj = (j < n - k - 3) ? kb + 3 + j : kb + (j - n + 3) * LD;
+                const int st = (j < n - k - 3) ? LD : 1;
+                const double w = tau * (H[jj] + u1 * H[jj + st] + u2 * H[jj + 2 * st]);
+                H[jj] -= w;
+                H[jj + st] -= w * u1;
+                H[jj + 2 * st] -= w * u2;
+              }
+              // corner block: rows k..k+2 from the left, then rows k..k+3 from the right
+#pragma unroll
+              for (int j = 0; j < 3; ++j) {
+                const double w = tau * (b[0][j] + u1 * b[1][j] + u2 * b[2][j]);
+                b[0][j] -= w;
+                b[1][j] -= w * u1;
+                b[2][j] -= w * u2;
+              }
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const double w = tau * (b[i][0] + u1 * b[i][1] + u2 * b[i][2]);
+                b[i][0] -= w;
+                b[i][1] -= w * u1;
+                b[i][2] -= w * u2;
+              }
+              if (lane == 0) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                  for (int j = 0; j < 3; ++j) H[kb + i * LD + j] = b[i][j];
+                if (k + 3 <= hh) {
+#pragma unroll
+                  for (int j = 0; j < 3; ++j) H[kb + 3 * LD + j] = b[3][j];
+                }
+                if (k > lo) {
+                  H[kb - 1] = beta;
+                  H[kb - 1 + LD] = 0.0;
+                  H[kb - 1 + 2 * LD] = 0.0;
+                }
+                rf[3 * k] = tau;
+                rf[3 * k + 1] = u1;
+                rf[3 * k + 2] = u2;
+              }
+              wave_sync();
+              x = b[1][0];
+              y = b[2][0];
+              z = b[3][0];
             }
-            if (!three) z = 0.0;
-            const double nrm = sqrt(x * x + y * y + z * z);
+          } else {
+          for (int k = lo; k < hh - 1; ++k) {
+            const bool row3 = k + 3 <= hh;
+            double b[4][3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) b[i][j] = HH(k + i, k + j);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) b[3][j] = row3 ? HH(k + 3, k + j) : 0.0;
+            // Off-block work as n - 3 uniform jobs of three elements each: job j < ncol is
+            // column k + 3 + j (rows k..k+2, left update), the rest are rows 0..k-1 (columns
+            // k..k+2, right update). The first two jobs of each lane are loaded up front.
+            const int ncol = n - k - 3, njob = n - 3;
+            int64_t ja = 0, jb = 0, sa = 1, sb = 1;
+            double va[3] = {0.0, 0.0, 0.0}, vb[3] = {0.0, 0.0, 0.0};
+            const bool ha = lane < njob, hb = lane + W0 < njob;
+            if (ha) {
+              const int j = lane;
+              ja = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(j - ncol) * ld + k;
+              sa = (j < ncol) ? ld : 1;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) va[i] = H[ja + i * sa];
+            }
+            if (hb) {
+              const int j = lane + W0;
+              jb = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(j - ncol) * ld + k;
+              sb = (j < ncol) ? ld : 1;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) vb[i] = H[jb + i * sb];
+            }
+            wave_sync();  // all loads of the step precede its stores
+            // Reflector (I - tau u u^T), u = (1, u1, u2), taking (x, y, z) to (beta, 0, 0) with
+            // beta = -sign(x) ||(x, y, z)||. Then tau = 1 + |x| / ||.|| and 1 / (x - beta) =
+            // sign(x) / (|x| + ||.||): one reciprocal square root and one reciprocal, each
+            // refined by two Newton steps.
             double tau = 0.0, u1 = 0.0, u2 = 0.0, beta = 0.0;
-            if (nrm != 0.0 && (y != 0.0 || z != 0.0)) {
-              beta = (x >= 0.0) ? -nrm : nrm;
-              tau = (beta - x) / beta;
-              const double sc = 1.0 / (x - beta);
-              u1 = y * sc;
-              u2 = z * sc;
-            }
-            wave_sync();  // every lane has read column k - 1 before lane 0 overwrites it
-            if (lane == 0) {
-              srefl[3 * k] = tau;
-              srefl[3 * k + 1] = u1;
-              srefl[3 * k + 2] = u2;
+            if (y != 0.0 || z != 0.0) {
+              double xs = x, ys = y, zs = z, unscale = 1.0;
+              double s2 = xs * xs + ys * ys + zs * zs;
+              if (s2 < 0x1p-900) {  // keep the squares clear of the subnormal range
+                xs *= 0x1p600;
+                ys *= 0x1p600;
+                zs *= 0x1p600;
+                unscale = 0x1p-600;
+                s2 = xs * xs + ys * ys + zs * zs;
+              }
+              double r = __builtin_amdgcn_rsq(s2);
+              const double h2 = 0.5 * s2;
+              r = r * fma(-h2 * r, r, 1.5);
+              r = r * fma(-h2 * r, r, 1.5);
+              const double nrm = s2 * r;
+              const double ax = fabs(xs);
+              tau = fma(ax, r, 1.0);
+              const double dd = ax + nrm;
+              double q = __builtin_amdgcn_rcp(dd);
+              q = fma(q, fma(-dd, q, 1.0), q);
+              q = fma(q, fma(-dd, q, 1.0), q);
+              const double sc = copysign(q, xs);
+              u1 = ys * sc;
+              u2 = zs * sc;
+              beta = -copysign(nrm, xs) * unscale;
             }
             if (tau != 0.0) {
-              if (lane == 0 && k > lo) {
+              if (ha) {
+                const double w = tau * (va[0] + u1 * va[1] + u2 * va[2]);
+                H[ja] = va[0] - w;
+                H[ja + sa] = va[1] - w * u1;
+                H[ja + 2 * sa] = va[2] - w * u2;
+              }
+              if (hb) {
+                const double w = tau * (vb[0] + u1 * vb[1] + u2 * vb[2]);
+                H[jb] = vb[0] - w;
+                H[jb + sb] = vb[1] - w * u1;
+                H[jb + 2 * sb] = vb[2] - w * u2;
+              }
+              for (int j = lane + 2 * W0; j < njob; j += W0) {
+                const int64_t jj = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(j - ncol) * ld + k;
+                const int64_t st = (j < ncol) ? ld : 1;
+                const double w = tau * (H[jj] + u1 * H[jj + st] + u2 * H[jj + 2 * st]);
+                H[jj] -= w;
+                H[jj + st] -= w * u1;
+                H[jj + 2 * st] -= w * u2;
+              }
+              // corner block: rows k..k+2 from the left, then rows k..k+3 from the right
+#pragma unroll
+              for (int j = 0; j < 3; ++j) {
+                const double w = tau * (b[0][j] + u1 * b[1][j] + u2 * b[2][j]);
+                b[0][j] -= w;
+                b[1][j] -= w * u1;
+                b[2][j] -= w * u2;
+              }
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const double w = tau * (b[i][0] + u1 * b[i][1] + u2 * b[i][2]);
+                b[i][0] -= w;
+                b[i][1] -= w * u1;
+                b[i][2] -= w * u2;
+              }
+              if (lane == 0) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                  for (int j = 0; j < 3; ++j) HH(k + i, k + j) = b[i][j];
+                if (row3) {
+#pragma unroll
+                  for (int j = 0; j < 3; ++j) HH(k + 3, k + j) = b[3][j];
+                }
+                if (k > lo) {
+                  HH(k, k - 1) = beta;
+                  HH(k + 1, k - 1) = 0.0;
+                  HH(k + 2, k - 1) = 0.0;
+                }
+              }
+            }
+            if (lane == 0) {
+              rf[3 * k] = tau;
+              rf[3 * k + 1] = u1;
+              rf[3 * k + 2] = u2;
+            }
+            wave_sync();
+            x = b[1][0];
+            y = b[2][0];
+            z = b[3][0];
+          }
+          }
+          {  // final two-element step k = hh - 1 on rows/columns hh-1, hh
+            const int k = hh - 1;
+            const double nrm = sqrt(x * x + y * y);
+            double tau = 0.0, u1 = 0.0, beta = 0.0;
+            if (nrm != 0.0 && y != 0.0) {
+              beta = (x >= 0.0) ? -nrm : nrm;
+              tau = (beta - x) / beta;
+              u1 = y / (x - beta);
+            }
+            if (tau != 0.0) {
+              if (lane == 0) {
                 HH(k, k - 1) = beta;
                 HH(k + 1, k - 1) = 0.0;
-                if (three) HH(k + 2, k - 1) = 0.0;
               }
-              for (int c = k + lane; c < n; c += W0) {  // rows k..k+2, columns right of k-1
-                if (three) {
-                  const double w = tau * (HH(k, c) + u1 * HH(k + 1, c) + u2 * HH(k + 2, c));
-                  HH(k, c) -= w;
-                  HH(k + 1, c) -= w * u1;
-                  HH(k + 2, c) -= w * u2;
-                } else {
-                  const double w = tau * (HH(k, c) + u1 * HH(k + 1, c));
-                  HH(k, c) -= w;
-                  HH(k + 1, c) -= w * u1;
-                }
+              for (int c = k + lane; c < n; c += W0) {
+                const double w = tau * (HH(k, c) + u1 * HH(k + 1, c));
+                HH(k, c) -= w;
+                HH(k + 1, c) -= w * u1;
               }
               wave_sync();
-              const int rmax = min(k + 3, hh);
-              for (int r = lane; r <= rmax; r += W0) {  // columns k..k+2, rows 0..k+3
-                if (three) {
-                  const double w = tau * (HH(r, k) + u1 * HH(r, k + 1) + u2 * HH(r, k + 2));
-                  HH(r, k) -= w;
-                  HH(r, k + 1) -= w * u1;
-                  HH(r, k + 2) -= w * u2;
-                } else {
-                  const double w = tau * (HH(r, k) + u1 * HH(r, k + 1));
-                  HH(r, k) -= w;
-                  HH(r, k + 1) -= w * u1;
-                }
+              for (int r = lane; r <= hh; r += W0) {
+                const double w = tau * (HH(r, k) + u1 * HH(r, k + 1));
+                HH(r, k) -= w;
+                HH(r, k + 1) -= w * u1;
               }
-              wave_sync();
             }
+            if (lane == 0) {
+              rf[3 * k] = tau;
+              rf[3 * k + 1] = u1;
+              rf[3 * k + 2] = 0.0;
+              zops[slot] = ZOp{1, lo, hh, 0};
+            }
+            wave_sync();
           }
+        } else if (act == kActRotate) {  // split a real 2x2 block with [[cs, -sn], [sn, cs]]
+          const int h1 = hh - 1;
+          const double cs = sxyz[0], sn = sxyz[1];
+          for (int c = h1 + lane; c < n; c += W0) {
+            const double x = HH(h1, c), y = HH(hh, c);
+            HH(h1, c) = cs * x + sn * y;
+            HH(hh, c) = -sn * x + cs * y;
+          }
+          wave_sync();
+          for (int r = lane; r <= hh; r += W0) {
+            const double x = HH(r, h1), y = HH(r, hh);
+            HH(r, h1) = cs * x + sn * y;
+            HH(r, hh) = -sn * x + cs * y;
+          }
+          wave_sync();
+          if (lane == 0) {
+            HH(hh, h1) = 0.0;
+            lre[h1] = HH(h1, h1);
+            lre[hh] = HH(hh, hh);
+            lim[h1] = 0.0;
+            lim[hh] = 0.0;
+            blk[h1] = 1;
+            blk[hh] = 1;
+            sctl[1] = hh - 2;
+            sctl[2] = 0;
+            rf[0] = cs;
+            rf[1] = sn;
+            zops[slot] = ZOp{2, 0, hh, 0};
+          }
+          wave_sync();
         }
       }
     }
-    __syncthreads();
-    const int act = sctl[4];
-    if (act == kActStop) break;
-    if (act == kActSweep) {
-      // delayed application of the sweep's reflectors to the rows of Z
-      const int lo = sctl[6], hh = sctl[0];
-      for (int r = tid; r < n; r += NT) {
-        double z0 = ZZ(r, lo), z1 = ZZ(r, lo + 1);
-        for (int k = lo; k <= hh - 1; ++k) {
-          const bool three = k < hh - 1;
-          double z2 = three ? ZZ(r, k + 2) : 0.0;
-          const double tau = srefl[3 * k];
-          if (tau != 0.0) {
-            const double u1 = srefl[3 * k + 1], u2 = srefl[3 * k + 2];
-            const double w = tau * (z0 + u1 * z1 + (three ? u2 * z2 : 0.0));
-            z0 -= w;
-            z1 -= w * u1;
-            if (three) z2 -= w * u2;
-          }
-          ZZ(r, k) = z0;
-          z0 = z1;
-          z1 = z2;
-        }
-        ZZ(r, hh) = z0;
-      }
-    } else if (act == kActRotate) {  // split a real 2x2 block with [[cs, -sn], [sn, cs]]
-      const int hh = sctl[0], h1 = hh - 1;
-      const double cs = sxyz[0], sn = sxyz[1];
-      for (int c = h1 + tid; c < n; c += NT) {
-        const double x = HH(h1, c), y = HH(hh, c);
-        HH(h1, c) = cs * x + sn * y;
-        HH(hh, c) = -sn * x + cs * y;
-      }
-      __syncthreads();
-      for (int r = tid; r < n; r += NT) {
-        if (r <= hh) {
-          const double x = HH(r, h1), y = HH(r, hh);
-          HH(r, h1) = cs * x + sn * y;
-          HH(r, hh) = -sn * x + cs * y;
-        }
-        const double zx = ZZ(r, h1), zy = ZZ(r, hh);
-        ZZ(r, h1) = cs * zx + sn * zy;
-        ZZ(r, hh) = -sn * zx + cs * zy;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        HH(hh, h1) = 0.0;
-        lre[h1] = HH(h1, h1);
-        lre[hh] = HH(hh, hh);
-        lim[h1] = 0.0;
-        lim[hh] = 0.0;
-        blk[h1] = 1;
-        blk[hh] = 1;
-        sctl[1] = hh - 2;
-        sctl[2] = 0;
-      }
+    if (split) {
+      if (!wave0 && iter > 0) apply_zop(zops[slot ^ 1], srefl + (slot ^ 1) * 3 * kMaxn, ZT, n, tid - 64, NT - 64);
+    } else {
+      wave_sync();
+      apply_zop(zops[slot], rf, ZT, n, tid, NT);
     }
     __syncthreads();
+    if (zops[slot].stop) break;
   }
   if (sctl[5]) {
     if (tid == 0) status[it.layer] = -5;
@@ -575,18 +873,17 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
 __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, int32_t* status) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
-  __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1)];
-  __shared__ double sv[kMaxn];
-  __shared__ double srefl[3 * kMaxn];
+  __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1) + 3 * 64];
+  __shared__ double srefl[2 * 3 * kMaxn];
   __shared__ double sred[8];
-  __shared__ int sredi[8];
   __shared__ int sctl[8];
   __shared__ double sxyz[3];
+  __shared__ ZOp zops[2];
   double* base = ws + it.ws;
   if (it.n <= kLdsMaxn)
-    eigen_body<true>(it, base, status, sH, sv, srefl, sred, sredi, sctl, sxyz);
+    eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops);
   else
-    eigen_body<false>(it, base, status, sH, sv, srefl, sred, sredi, sctl, sxyz);
+    eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops);
 }
 
 }  // namespace vbrdf
