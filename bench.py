@@ -36,8 +36,10 @@ def stage_work(stage, layers):
                 fl += 25.0 * n ** 3           # real Schur form + eigenvectors (Golub-Van Loan count)
             elif stage in ("gemm_FE", "gemm_U", "gemm_V"):
                 fl += 2.0 * n ** 3
-            elif stage == "rdiv":
-                fl += 2 * (2.0 / 3.0 * n ** 3 + 2.0 * n ** 3)  # two LU + two n-RHS right divisions
+            elif stage == "lu":
+                fl += 2 * (2.0 / 3.0 * n ** 3)               # LU of S' and T'
+            elif stage == "trsm":
+                fl += 2 * (2.0 * n ** 3)                     # two n-RHS right divisions
             elif stage == "assemble":
                 fl += N * N * (L - m) * 72.0  # 36 products-with-coefficient per degree and block pair
         if stage == "synth":

@@ -20,10 +20,11 @@ using namespace vbrdf;
 
 namespace {
 
-constexpr int kNumStages = 13;
+constexpr int kNumStages = 14;
 constexpr int kTimedSolves = 256;  // solves whose stage events are kept between queries
-const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen",   "gemm_U", "gemm_V",
-                                             "vfix",     "colscal",  "bcbuild",  "rdiv",    "response", "synth"};
+const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen",
+                                             "gemm_U",   "gemm_V",   "vfix",     "colscal", "bcbuild",
+                                             "lu",       "trsm",     "response", "synth"};
 
 thread_local std::string g_err;
 
@@ -98,6 +99,8 @@ struct vbrdf_plan {
   int n_items = 0;
   int max_n = 0;
   int max_N = 0;
+  int trsm_tiles = 0;     // row tiles of the right division (largest item)
+  size_t trsm_lds = 0;   // its LDS bytes
   int precision = VBRDF_PRECISION_FP64;
   size_t out_doubles = 0;
   size_t ws_bytes = 0;
@@ -196,6 +199,8 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     for (int i = 0; i < ly.N; ++i)
       for (int q = 0; q < ly.N; ++q) tasks.push_back(SynthTask{l, i, q, 0});
     p->max_n = std::max(p->max_n, n);
+    p->trsm_tiles = std::max(p->trsm_tiles, (n + trsm_rows(n) - 1) / trsm_rows(n));
+    p->trsm_lds = std::max(p->trsm_lds, sizeof(double) * (size_t)n * (trsm_rows(n) + 3));
     p->max_N = std::max(p->max_N, ly.N);
     coef_off += 6 * (int64_t)ly.L;
     out_off += (int64_t)ly.N * ly.N * ly.n_dphi * 16;
@@ -226,6 +231,14 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
         delete p;
         return fail(VBRDF_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(ee));
       }
+    }
+  }
+  if (p->trsm_lds > 65536) {  // the right-division tile of a large system exceeds the default LDS cap
+    const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trsm),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->trsm_lds);
+    if (ea != hipSuccess) {
+      delete p;
+      return fail(VBRDF_E_DEVICE, "hipFuncSetAttribute(k_trsm): %s", hipGetErrorString(ea));
     }
   }
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->ws_d), p->ws_bytes);
@@ -285,7 +298,9 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
   const int et = (mn + 15) / 16;
   k_bcbuild<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_rdiv<<<dim3(ni, 2), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_lu<<<dim3(ni, 2), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  mark();
+  k_trsm<<<dim3(p->trsm_tiles, 2, ni), 64, p->trsm_lds, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
   mark();

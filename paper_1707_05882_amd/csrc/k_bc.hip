@@ -110,8 +110,6 @@ __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status) 
   }
 }
 
-constexpr int kRows = 16;  // right-hand-side rows per LDS pass
-
 __device__ inline void block_argmax(double v, int idx, double* sv, int* si) {
   // leaves the winner in sv[0], si[0]; ties resolve to the smaller index
   for (int o = 32; o > 0; o >>= 1) {
@@ -180,102 +178,173 @@ __device__ __forceinline__ bool lu_factor(double* A, int64_t ld, int n, int* per
     for (int i = k + 1 + tid; i < n; i += NT) A[(int64_t)i * ld + k] *= inv;
     if (tid == 0) invd[k] = inv;
     __syncthreads();
-    const int m = n - k - 1;
-    for (int t = tid; t < m * m; t += NT) {
-      const int i = k + 1 + t / m, c = k + 1 + t % m;
-      A[(int64_t)i * ld + c] -= A[(int64_t)i * ld + k] * A[(int64_t)k * ld + c];
+    // trailing update: lane l of wave w takes columns k+1+l, k+1+l+64, ... and rows k+1+w,
+    // k+1+w+nw, ... (no index division; A(i, k) is the same address for a whole wave). The
+    // block size is a multiple of 64 (or below 64).
+    const int W = NT < 64 ? NT : 64, lane = tid % W, wv = tid / W, nw = NT / W;
+    for (int c = k + 1 + lane; c < n; c += W) {
+      const double akc = A[(int64_t)k * ld + c];
+      for (int i = k + 1 + wv; i < n; i += nw) A[(int64_t)i * ld + c] -= A[(int64_t)i * ld + k] * akc;
     }
     __syncthreads();
   }
   return true;
 }
 
-constexpr int kLuLds = kLdsMaxn * (kLdsMaxn + 1);                 // LDS matrix
-constexpr int kRhsLds = kRows * (kMaxn + 1);                       // LDS right-hand-side tile
-constexpr int kBcLds = (kLuLds + kRows * (kLdsMaxn + 1) > kRhsLds) ? kLuLds + kRows * (kLdsMaxn + 1) : kRhsLds;
+constexpr int kLuLds = kLdsMaxn * (kLdsMaxn + 1);  // LDS matrix
+constexpr int kVfixLds = kLuLds + kLdsMaxn;          // LDS matrix and one work vector
 
-// Y = U A^-1 for one item: factor A (in LDS when kLds), then right-divide kRows rows of U at a time.
-template <bool kLds>
-__device__ __forceinline__ void rdiv_body(const Item& it, double* Ag, const double* __restrict__ U,
-                                          double* __restrict__ Y, int32_t* status, double* smem, int* perm,
-                                          double* invd, double* redv, int* redi) {
-  const int n = it.n;
-  const int tid = threadIdx.x, NT = blockDim.x;
-  double* A = kLds ? smem : Ag;
-  const int64_t ld = kLds ? n + 1 : n;
-  const int ldb = n + 1;  // padded: rows of the right-hand-side tile fall in distinct LDS banks
-  double* B = kLds ? smem + kLuLds : smem;  // [kRows][n + 1]
-  if (kLds) {
-    for (int t = tid; t < n * n; t += NT) A[(int64_t)(t / n) * ld + (t % n)] = Ag[t];
-    __syncthreads();
-  }
-  if (!lu_factor(A, ld, n, perm, invd, redv, redi)) {
-    if (tid == 0) status[it.layer] = -5;
-    return;
-  }
-#define AA(r, c) A[(int64_t)(r) * ld + (c)]
-#define BB(r, c) B[(int64_t)(r) * ldb + (c)]
-  for (int r0 = 0; r0 < n; r0 += kRows) {
-    const int nr = min(kRows, n - r0);
-    for (int t = tid; t < kRows * n; t += NT) {
-      const int r = t / n, c = t % n;
-      BB(r, c) = (r < nr) ? U[(int64_t)(r0 + r) * n + c] : 0.0;
-    }
-    __syncthreads();
-    // z Uu = u, column by column: z_j = u_j / Uu_jj, then u_c -= z_j Uu_jc for c > j
-    for (int j = 0; j + 1 < n; ++j) {
-      const int m = n - j - 1;
-      const double ijj = invd[j];
-      for (int t = tid; t < kRows * m; t += NT) {
-        const int r = t % kRows, c = j + 1 + t / kRows;
-        BB(r, c) -= BB(r, j) * ijj * AA(j, c);
-      }
-      __syncthreads();
-    }
-    for (int t = tid; t < kRows * n; t += NT) {
-      const int r = t % kRows, c = t / kRows;
-      BB(r, c) *= invd[c];
-    }
-    __syncthreads();
-    // w L = z with unit lower L, from the last column: w_j = z_j, then z_c -= w_j L_jc for c < j
-    for (int j = n - 1; j >= 1; --j) {
-      for (int t = tid; t < kRows * j; t += NT) {
-        const int r = t % kRows, c = t / kRows;
-        BB(r, c) -= BB(r, j) * AA(j, c);
-      }
-      __syncthreads();
-    }
-    for (int t = tid; t < nr * n; t += NT) {
-      const int r = t / n, k = t % n;
-      Y[(int64_t)(r0 + r) * n + perm[k]] = BB(r, k);
-    }
-    __syncthreads();
-  }
-#undef AA
-#undef BB
+// Per-item scratch of the boundary solve, in the extras block: 1 / Uu_kk of S' and T'
+// (2 x n doubles) and the two pivot orders (2 x n int32 in n doubles).
+__device__ inline double* lu_invd(double* ex, int n, int which) { return ex + (4 + which) * (int64_t)n; }
+__device__ inline int* lu_perm(double* ex, int n, int which) {
+  return reinterpret_cast<int*>(ex + 2 * (int64_t)n) + which * n;
 }
 
-// LU factorisation with partial pivoting of A (S' or T') and the right division Y = U A^-1.
-// blockIdx.y selects S' (0) or T' (1). With P^T A = L Uu (row perm[k] of A at position k),
-// Y A = U becomes W L Uu = U for W = Y P, i.e. Y[:, perm[k]] = W[:, k].
-__global__ __launch_bounds__(256) void k_rdiv(const Item* items, double* ws, int32_t* status) {
+// LU factorisation with partial pivoting of S' (blockIdx.y = 0) or T' (1), P^T A = L Uu. The
+// factor is written transposed, AT[j n + c] = A(c, j), so that column j of Uu (c < j) and of L
+// (c > j) are contiguous for the right division; pivots and 1 / Uu_kk go to the extras block.
+__global__ __launch_bounds__(256) void k_lu(const Item* items, double* ws, int32_t* status) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
-  const int n = it.n;
+  const int n = it.n, tid = threadIdx.x, NT = blockDim.x;
   const int which = blockIdx.y;
   double* base = ws + it.ws;
   double* Ag = base + (int64_t)(which == 0 ? kBufZ : kBufX) * n * n;
-  const double* U = base + (int64_t)kBufU * n * n;
-  double* Y = base + (int64_t)(which == 0 ? kBufYS : kBufYT) * n * n;
-  __shared__ double smem[kBcLds];
+  double* AT = base + (int64_t)(which == 0 ? kBufG : kBufF) * n * n;
+  double* ex = base + extras_off(n);
+  __shared__ double smem[kLuLds];
   __shared__ int perm[kMaxn];
   __shared__ double invd[kMaxn];
   __shared__ double redv[8];
   __shared__ int redi[8];
-  if (n <= kLdsMaxn)
-    rdiv_body<true>(it, Ag, U, Y, status, smem, perm, invd, redv, redi);
-  else
-    rdiv_body<false>(it, Ag, U, Y, status, smem, perm, invd, redv, redi);
+  const bool in_lds = n <= kLdsMaxn;
+  double* A = in_lds ? smem : Ag;
+  const int64_t ld = in_lds ? n + 1 : n;
+  bool ok;
+  if (in_lds) {
+    for (int t = tid; t < n * n; t += NT) smem[(t / n) * (n + 1) + (t % n)] = Ag[t];
+    __syncthreads();
+    ok = lu_factor(smem, n + 1, n, perm, invd, redv, redi);
+  } else {
+    ok = lu_factor(Ag, n, n, perm, invd, redv, redi);
+  }
+  if (!ok) {
+    if (tid == 0) status[it.layer] = -5;
+    return;
+  }
+  for (int t = tid; t < n * n; t += NT) {
+    const int j = t / n, c = t % n;
+    AT[t] = A[(int64_t)c * ld + j];
+  }
+  double* id = lu_invd(ex, n, which);
+  int* pm = lu_perm(ex, n, which);
+  for (int i = tid; i < n; i += NT) {
+    id[i] = invd[i];
+    pm[i] = perm[i];
+  }
+}
+
+// Right division Y = U A^-1 with the factors of k_lu, for S' and T' (blockIdx.y) and a tile of
+// R rows of U (blockIdx.x). One wave; lane r owns row r of the tile, kept in LDS as Bt[c][r]
+// (row stride R + 1), and solves it on its own: no workgroup barrier. With W = Y P:
+//   Z Uu = U :  Z_j = (U_j - sum_{c<j} Z_c Uu_cj) / Uu_jj      (j ascending)
+//   W L = Z  :  W_j = Z_j - sum_{c>j} W_c L_cj                 (j descending, unit L)
+// and Y[:, perm[j]] = W[:, j]. The factor entries are the same for all lanes.
+__global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int32_t* status) {
+  const Item it = items[blockIdx.z];
+  if (status[it.layer] != 0) return;
+  const int n = it.n, lane = threadIdx.x;
+  const int R = trsm_rows(n);
+  const int r0 = blockIdx.x * R;
+  if (r0 >= n) return;
+  const int which = blockIdx.y;
+  double* base = ws + it.ws;
+  const double* __restrict__ AT = base + (int64_t)(which == 0 ? kBufG : kBufF) * n * n;
+  const double* __restrict__ U = base + (int64_t)kBufU * n * n;
+  double* __restrict__ Y = base + (int64_t)(which == 0 ? kBufYS : kBufYT) * n * n;
+  double* ex = base + extras_off(n);
+  const double* __restrict__ id = lu_invd(ex, n, which);
+  const int* __restrict__ pm = lu_perm(ex, n, which);
+  // LDS: Bt [n][R + 1] (lane r's row of the tile down column r), then two factor-column buffers
+  HIP_DYNAMIC_SHARED(double, smem)
+  const int ldb = R + 1;
+  double* Bt = smem;
+  double* cb = smem + (int64_t)n * ldb;  // [2][n]
+  const int nr = min(R, n - r0);
+  for (int rr = 0; rr < nr; ++rr)
+    for (int c = lane; c < n; c += 64) Bt[c * ldb + rr] = U[(int64_t)(r0 + rr) * n + c];
+  // Each step j reads factor column j from LDS (the same address in all lanes) while the wave's
+  // loads of the next column are in flight.
+  double pre[kMaxn / 64];
+  auto fetch = [&](int j) {
+#pragma unroll
+    for (int q = 0; q < kMaxn / 64; ++q) {
+      const int c = lane + 64 * q;
+      if (c < n) pre[q] = AT[(int64_t)j * n + c];
+    }
+  };
+  auto stash = [&](double* dst) {
+#pragma unroll
+    for (int q = 0; q < kMaxn / 64; ++q) {
+      const int c = lane + 64 * q;
+      if (c < n) dst[c] = pre[q];
+    }
+  };
+  auto sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+  double* b = Bt + lane;
+  const bool own = lane < nr;
+  // Z Uu = U, j ascending
+  fetch(0);
+  stash(cb);
+  sync();
+  for (int j = 0; j < n; ++j) {
+    const double* col = cb + (j & 1) * n;
+    if (j + 1 < n) fetch(j + 1);
+    if (own) {
+      double a0 = b[j * ldb], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int c = 0;
+      for (; c + 4 <= j; c += 4) {
+        a0 -= b[c * ldb] * col[c];
+        a1 -= b[(c + 1) * ldb] * col[c + 1];
+        a2 -= b[(c + 2) * ldb] * col[c + 2];
+        a3 -= b[(c + 3) * ldb] * col[c + 3];
+      }
+      for (; c < j; ++c) a0 -= b[c * ldb] * col[c];
+      b[j * ldb] = ((a0 + a1) + (a2 + a3)) * id[j];
+    }
+    sync();  // every lane is done with the buffer the next stash overwrites
+    if (j + 1 < n) stash(cb + ((j + 1) & 1) * n);
+    sync();
+  }
+  // W L = Z, j descending (unit diagonal)
+  fetch(n - 1);
+  stash(cb + ((n - 1) & 1) * n);
+  sync();
+  for (int j = n - 1; j >= 0; --j) {
+    const double* col = cb + (j & 1) * n;
+    if (j > 0) fetch(j - 1);
+    if (own && j < n - 1) {
+      double a0 = b[j * ldb], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int c = j + 1;
+      for (; c + 4 <= n; c += 4) {
+        a0 -= b[c * ldb] * col[c];
+        a1 -= b[(c + 1) * ldb] * col[c + 1];
+        a2 -= b[(c + 2) * ldb] * col[c + 2];
+        a3 -= b[(c + 3) * ldb] * col[c + 3];
+      }
+      for (; c < n; ++c) a0 -= b[c * ldb] * col[c];
+      b[j * ldb] = (a0 + a1) + (a2 + a3);
+    }
+    sync();
+    if (j > 0) stash(cb + ((j - 1) & 1) * n);
+    sync();
+  }
+  for (int rr = 0; rr < nr; ++rr)
+    for (int c = lane; c < n; c += 64) Y[(int64_t)(r0 + rr) * n + pm[c]] = Bt[c * ldb + rr];
 }
 
 // Columns of V = E~ U that lost more than ~7 digits to cancellation (the conservation mode of
@@ -397,7 +466,7 @@ __global__ __launch_bounds__(256) void k_vfix(const Item* items, double* ws, int
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
   double* base = ws + it.ws;
-  __shared__ double smem[kBcLds];
+  __shared__ double smem[kVfixLds];
   __shared__ int perm[kMaxn];
   __shared__ double invd[kMaxn];
   __shared__ double redv[8];

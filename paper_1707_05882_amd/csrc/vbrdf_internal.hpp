@@ -73,7 +73,10 @@ __global__ void k_eigen(const Item* items, double* ws, int32_t* status);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
-__global__ void k_rdiv(const Item* items, double* ws, int32_t* status);
+__global__ void k_lu(const Item* items, double* ws, int32_t* status);
+__global__ void k_trsm(const Item* items, double* ws, int32_t* status);
+// right-hand-side rows per right-division tile (one wave; n x (rows + 3) doubles of LDS)
+__host__ __device__ inline int trsm_rows(int n) { return n <= 256 ? 64 : 32; }
 __global__ void k_response(const Item* items, const Layer* layers, const double* quad, double* ws,
                            const int32_t* status);
 __global__ void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
