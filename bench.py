@@ -51,6 +51,38 @@ def stage_work(stage, layers):
     return "alu", fl, "TFLOP/s"
 
 
+KERNEL_SOURCE = {"k_eigen": "k_eigen.hip", "k_lu": "k_bc.hip", "k_trsm": "k_bc.hip", "k_vfix": "k_bc.hip",
+                 "k_bcbuild": "k_bc.hip", "k_colscal": "k_bc.hip", "k_response": "k_bc.hip", "k_gemm": "k_gemm.hip",
+                 "k_assemble": "k_assemble.hip", "k_legendre": "k_assemble.hip", "k_validate": "k_assemble.hip",
+                 "k_synth": "k_synth.hip"}
+
+
+def stage_kernel(stage):
+    return "k_gemm" if stage.startswith("gemm") else f"k_{stage}"
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the recorded byte counters of this workload
+    (profiles/traffic_<workload>.txt), or None when there is no record or the kernel's sources
+    have changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCE:
+        return None
+    h = hashlib.sha256()
+    for part in (KERNEL_SOURCE[kernel], "vbrdf_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1707_05882_amd", "csrc", part), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()[:16]
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 5 and f[0] == kernel:
+                return float(f[4]) if f[1] == sha else None
+    return None
+
+
 def cpu_baseline(layers, units):
     from threadpoolctl import threadpool_info
 
@@ -72,7 +104,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="particulate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+
+        x = torch.ones(args.copy_probe * 2 ** 17, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 8, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (orders and layers are "
               "independent, so a multi-GPU run would shard them; that path is not built).", file=sys.stderr)
@@ -130,8 +174,9 @@ def main():
         achieved, peak = work / dur_s / 1e9, PEAK_HBM_GBS
     else:
         achieved, peak = work / dur_s / 1e12, PEAK_FP64_TFLOPS
+    kernel = stage_kernel(dom_stage)
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-                "traffic": None, "kernel": f"k_{dom_stage.split('_')[0]}" if dom_stage.startswith("gemm") else f"k_{dom_stage}",
+                "traffic": measured_traffic(kernel, layers.name), "kernel": kernel,
                 "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
 
     out = {
