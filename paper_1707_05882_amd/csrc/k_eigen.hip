@@ -100,7 +100,14 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Action codes of the QR driver (sctl[4]).
-enum : int { kActDeflated = 0, kActSweep = 1, kActRotate = 2, kActStop = 3 };
+enum : int { kActDeflated = 0, kActSweep = 1, kActRotate = 2, kActStop = 3, kActMulti = 4 };
+
+// Multi-bulge passes: with at least kMultiMin active rows and fewer than kMultiIts iterations since
+// the last deflation, one pass chases one bulge per wave (up to 4 double shifts at once), the
+// bulges kMultiGap rows apart. Otherwise a single double-shift sweep runs on wave 0.
+constexpr int kMultiMin = 32;
+constexpr int kMultiIts = 6;
+constexpr int kMultiGap = 4;
 
 // Z-update descriptor of one QR iteration, produced by wave 0 and applied by the other waves
 // during the next iteration (double-buffered): kind 0 none, 1 sweep (reflectors of steps lo..hh-1
@@ -109,7 +116,7 @@ enum : int { kActDeflated = 0, kActSweep = 1, kActRotate = 2, kActStop = 3 };
 // iteration; it lives in the double-buffered slot so that wave 0 cannot overwrite it (in the
 // next iteration) before every wave has read it.
 struct ZOp {
-  int kind, lo, hh, stop;
+  int kind, lo, hh, stop, nb;  // nb > 0: multi-bulge pass over lo..hh with nb bulges (no Z op)
 };
 
 // Applies one ZOp to rows t0, t0 + nt, ... of Z (Z(r, c) at ZT[c * n + r]).
@@ -276,12 +283,13 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
   // orthogonal factor is updated one iteration behind by the other waves, from the reflectors
   // wave 0 left in LDS, so the two overlap. With a single wave the update follows at once.
   const bool split = NT > 64;
+  const int nwave = (NT % 64 == 0) ? NT / 64 : 0;  // waves available for multi-bulge passes
   if (tid == 0) {
     sctl[1] = n - 1;  // active bottom index hh
     sctl[2] = 0;      // iterations since last deflation
     sctl[3] = 0;      // total iterations
     sctl[5] = 0;      // failure flag
-    zops[0] = zops[1] = ZOp{0, 0, 0, 0};
+    zops[0] = zops[1] = ZOp{0, 0, 0, 0, 0};
   }
   __syncthreads();
   for (int iter = 0;; ++iter) {
@@ -290,7 +298,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     if (wave0) {
       const int hh = __builtin_amdgcn_readfirstlane(sctl[1]);
       if (hh < 0) {
-        if (lane == 0) zops[slot] = ZOp{0, 0, 0, 1};
+        if (lane == 0) zops[slot] = ZOp{0, 0, 0, 1, 0};
       } else {
         int cand = 0;
         for (int k = 1 + lane; k <= hh; k += W0) {
@@ -315,7 +323,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
         }
         const int l = wave_max(cand);
         if (lane == 0) {
-          zops[slot] = ZOp{0, 0, 0, 0};
+          zops[slot] = ZOp{0, 0, 0, 0, 0};
           if (l > 0) HH(l, l - 1) = 0.0;
           if (l == hh) {  // 1x1 block
             lre[hh] = HH(hh, hh);
@@ -360,6 +368,32 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               sctl[1] = -1;
               sctl[4] = kActStop;
               zops[slot].stop = 1;
+            } else if (nwave >= 2 && its < kMultiIts && hh - l + 1 >= kMultiMin) {
+              // one shift pair per bulge: the eigenvalues of the 2x2 diagonal blocks ending at
+              // rows hh, hh - 2, ... (both roots of a real pair), stored in this slot's buffer
+              const int nb = nwave < 4 ? nwave : 4;
+              for (int bq = 0; bq < nb; ++bq) {
+                const int j = hh - 2 * bq;
+                const double a = HH(j - 1, j - 1), b = HH(j - 1, j), c = HH(j, j - 1), d = HH(j, j);
+                const double p = 0.5 * (a - d), bc = b * c, disc = p * p + bc;
+                double s1r, s1i, s2r, s2i;
+                if (disc >= 0.0) {
+                  const double zz = p + copysign(sqrt(disc), p);
+                  s1r = d + zz;
+                  s2r = (zz != 0.0) ? d - bc / zz : d;
+                  s1i = s2i = 0.0;
+                } else {
+                  s1r = s2r = d + p;
+                  s1i = sqrt(-disc);
+                  s2i = -s1i;
+                }
+                rf[4 * bq] = s1r;
+                rf[4 * bq + 1] = s1i;
+                rf[4 * bq + 2] = s2r;
+                rf[4 * bq + 3] = s2i;
+              }
+              zops[slot] = ZOp{0, l, hh, 0, nb};
+              sctl[4] = kActMulti;
             } else {
               double h11, h12, h21, h22;
               if (its % 20 == 10) {
@@ -699,7 +733,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               rf[3 * k] = tau;
               rf[3 * k + 1] = u1;
               rf[3 * k + 2] = 0.0;
-              zops[slot] = ZOp{1, lo, hh, 0};
+              zops[slot] = ZOp{1, lo, hh, 0, 0};
             }
             wave_sync();
           }
@@ -730,7 +764,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
             sctl[2] = 0;
             rf[0] = cs;
             rf[1] = sn;
-            zops[slot] = ZOp{2, 0, hh, 0};
+            zops[slot] = ZOp{2, 0, hh, 0, 0};
           }
           wave_sync();
         }
@@ -743,7 +777,126 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       apply_zop(zops[slot], rf, ZT, n, tid, NT);
     }
     __syncthreads();
-    if (zops[slot].stop) break;
+    const ZOp op = zops[slot];  // not rewritten before the barrier of the next iteration
+    if (op.nb > 0) {
+      // Multi-bulge pass: wave b chases bulge b, kMultiGap rows behind bulge b - 1. A chain step
+      // moves every bulge one row: each wave forms its reflector (from column k - 1, or from the
+      // shift polynomial when it enters at row lo), applies it from the left to rows k..k+2,
+      // then after a barrier from the right to columns k..k+2 of H and Z. Rows of different
+      // bulges in a left phase and columns in a right phase are disjoint, and a bulge's
+      // reflector input is not touched by the neighbours within a step (gap >= 4).
+      const int lo = op.lo, hh = op.hh, nb = op.nb, wv = tid >> 6;
+      const double* sh = srefl + slot * 3 * kMaxn;
+      const int nsteps = (hh - lo) + kMultiGap * (nb - 1);
+      for (int t = 0; t < nsteps; ++t) {
+        const int k = lo + t - kMultiGap * wv;
+        const bool on = wv < nb && k >= lo && k <= hh - 1;
+        const bool three = k < hh - 1;
+        double tau = 0.0, u1 = 0.0, u2 = 0.0, beta = 0.0;
+        if (on) {
+          double x, y, z;
+          if (k == lo) {
+            const double s1r = sh[4 * wv], s1i = sh[4 * wv + 1], s2r = sh[4 * wv + 2], s2i = sh[4 * wv + 3];
+            const double a0 = HH(lo, lo), a1 = HH(lo + 1, lo);
+            const double sc = fabs(a0 - s2r) + fabs(s2i) + fabs(a1);
+            const double a1s = a1 / sc;
+            x = a1s * HH(lo, lo + 1) + (a0 - s1r) * ((a0 - s2r) / sc) - s1i * (s2i / sc);
+            y = a1s * (a0 + HH(lo + 1, lo + 1) - s1r - s2r);
+            z = a1s * HH(lo + 2, lo + 1);
+          } else {
+            x = HH(k, k - 1);
+            y = HH(k + 1, k - 1);
+            z = three ? HH(k + 2, k - 1) : 0.0;
+          }
+          wave_sync();  // every lane has read its input before the left phase overwrites it
+          beta = x;
+          if (y != 0.0 || z != 0.0) {
+            double xs = x, ys = y, zs = z, unscale = 1.0;
+            double s2 = xs * xs + ys * ys + zs * zs;
+            if (s2 < 0x1p-900) {
+              xs *= 0x1p600;
+              ys *= 0x1p600;
+              zs *= 0x1p600;
+              unscale = 0x1p-600;
+              s2 = xs * xs + ys * ys + zs * zs;
+            }
+            double r = __builtin_amdgcn_rsq(s2);
+            const double h2 = 0.5 * s2;
+            r = r * fma(-h2 * r, r, 1.5);
+            r = r * fma(-h2 * r, r, 1.5);
+            const double nrm = s2 * r;
+            const double ax = fabs(xs);
+            tau = fma(ax, r, 1.0);
+            const double dd = ax + nrm;
+            double q = __builtin_amdgcn_rcp(dd);
+            q = fma(q, fma(-dd, q, 1.0), q);
+            q = fma(q, fma(-dd, q, 1.0), q);
+            const double sc = copysign(q, xs);
+            u1 = ys * sc;
+            u2 = zs * sc;
+            beta = -copysign(nrm, xs) * unscale;
+          }
+          if (tau != 0.0) {
+            if (lane == 0 && k > lo) {
+              HH(k, k - 1) = beta;
+              HH(k + 1, k - 1) = 0.0;
+              if (three) HH(k + 2, k - 1) = 0.0;
+            }
+            if (three) {
+              for (int c = k + lane; c < n; c += 64) {
+                const double h0 = HH(k, c), h1 = HH(k + 1, c), h2 = HH(k + 2, c);
+                const double w = tau * (h0 + u1 * h1 + u2 * h2);
+                HH(k, c) = h0 - w;
+                HH(k + 1, c) = h1 - w * u1;
+                HH(k + 2, c) = h2 - w * u2;
+              }
+            } else {
+              for (int c = k + lane; c < n; c += 64) {
+                const double h0 = HH(k, c), h1 = HH(k + 1, c);
+                const double w = tau * (h0 + u1 * h1);
+                HH(k, c) = h0 - w;
+                HH(k + 1, c) = h1 - w * u1;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (on && tau != 0.0) {
+          const int rmax = min(k + 3, hh);
+          if (three) {
+            for (int r = lane; r <= rmax; r += 64) {
+              const double h0 = HH(r, k), h1 = HH(r, k + 1), h2 = HH(r, k + 2);
+              const double w = tau * (h0 + u1 * h1 + u2 * h2);
+              HH(r, k) = h0 - w;
+              HH(r, k + 1) = h1 - w * u1;
+              HH(r, k + 2) = h2 - w * u2;
+            }
+            for (int r = lane; r < n; r += 64) {
+              const double z0 = ZZ(r, k), z1 = ZZ(r, k + 1), z2 = ZZ(r, k + 2);
+              const double w = tau * (z0 + u1 * z1 + u2 * z2);
+              ZZ(r, k) = z0 - w;
+              ZZ(r, k + 1) = z1 - w * u1;
+              ZZ(r, k + 2) = z2 - w * u2;
+            }
+          } else {
+            for (int r = lane; r <= rmax; r += 64) {
+              const double h0 = HH(r, k), h1 = HH(r, k + 1);
+              const double w = tau * (h0 + u1 * h1);
+              HH(r, k) = h0 - w;
+              HH(r, k + 1) = h1 - w * u1;
+            }
+            for (int r = lane; r < n; r += 64) {
+              const double z0 = ZZ(r, k), z1 = ZZ(r, k + 1);
+              const double w = tau * (z0 + u1 * z1);
+              ZZ(r, k) = z0 - w;
+              ZZ(r, k + 1) = z1 - w * u1;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (op.stop) break;
   }
   if (sctl[5]) {
     if (tid == 0) status[it.layer] = -5;
