@@ -36,6 +36,8 @@ def stage_work(stage, layers):
                 fl += 25.0 * n ** 3           # real Schur form + eigenvectors (Golub-Van Loan count)
             elif stage in ("gemm_FE", "gemm_U", "gemm_V"):
                 fl += 2.0 * n ** 3
+            elif stage == "hqapply":
+                fl += 2.0 * n ** 3                           # n - 2 reflectors applied to n columns
             elif stage == "lu":
                 fl += 2 * (2.0 / 3.0 * n ** 3)               # LU of S' and T'
             elif stage == "trsm":
@@ -51,7 +53,7 @@ def stage_work(stage, layers):
     return "alu", fl, "TFLOP/s"
 
 
-KERNEL_SOURCE = {"k_eigen": "k_eigen.hip", "k_lu": "k_bc.hip", "k_trsm": "k_bc.hip", "k_vfix": "k_bc.hip",
+KERNEL_SOURCE = {"k_eigen": "k_eigen.hip", "k_hqapply": "k_eigen.hip", "k_lu": "k_bc.hip", "k_trsm": "k_bc.hip", "k_vfix": "k_bc.hip",
                  "k_bcbuild": "k_bc.hip", "k_colscal": "k_bc.hip", "k_response": "k_bc.hip", "k_gemm": "k_gemm.hip",
                  "k_assemble": "k_assemble.hip", "k_legendre": "k_assemble.hip", "k_validate": "k_assemble.hip",
                  "k_synth": "k_synth.hip"}

@@ -20,11 +20,11 @@ using namespace vbrdf;
 
 namespace {
 
-constexpr int kNumStages = 14;
+constexpr int kNumStages = 15;
 constexpr int kTimedSolves = 256;  // solves whose stage events are kept between queries
 const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen",
-                                             "gemm_U",   "gemm_V",   "vfix",     "colscal", "bcbuild",
-                                             "lu",       "trsm",     "response", "synth"};
+                                             "gemm_U",   "hqapply",  "gemm_V",   "vfix",    "colscal",
+                                             "bcbuild",  "lu",       "trsm",     "response", "synth"};
 
 thread_local std::string g_err;
 
@@ -287,7 +287,9 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
   mark();
   k_eigen<<<ni, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufU, layer_status);  // U = Z X
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufG, layer_status);  // U' = Z X
+  mark();
+  k_hqapply<<<dim3((mn + 15) / 16, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);  // U = Q U'
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, layer_status);  // V = E~ U
   mark();

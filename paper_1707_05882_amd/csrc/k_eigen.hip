@@ -15,7 +15,8 @@
 // The matrix is not balanced: F E = M^-1 X- M^-1 X+ is graded by the 1/mu factors, and a diagonal
 // power-of-two balancing loses about two digits on its smallest (diffusion-mode) eigenvalues,
 // which dominate the response; without it the eigenpairs reach about 1e-11 relative.
-// The caller then forms U = Z X_T with a GEMM. Output convention: for a complex pair stored at
+// The caller then forms U' = Z X_T with a GEMM and U = Q U' with k_hqapply (Q from the
+// Hessenberg reduction). Output convention: for a complex pair stored at
 // (j, j+1) with Im lambda_j > 0, U[:, j] + i U[:, j+1] is the eigenvector of lambda_j.
 //
 // H is kept in LDS (row stride n + 1) when n <= 128 and reduced in place in global memory
@@ -210,25 +211,44 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
   const double hnorm = sxyz[0];
   __syncthreads();
 
-  // ---- 1. Householder reduction to Hessenberg form, Z accumulated. Each dot product of the
-  // two-sided update is split over P adjacent lanes (combined by lane exchange) so that all
-  // threads work although a step has at most n columns and n rows.
+  // ---- 1. Householder reduction to Hessenberg form. Z is not accumulated here: v_k and tau_k
+  // of every step go to the workspace (QV) and k_hqapply applies them to the eigenvectors, so the
+  // QR phase starts from Z = I. Each dot product of the two-sided update is split over P adjacent
+  // lanes (combined by lane exchange) so that all threads work although a step has at most n
+  // columns and n rows. The column below the subdiagonal is kept raw in sv (v_0 = 1 and
+  // v_i = sv[i] / (x0 - beta)), which lets its norm and its copy share one barrier.
+  double* __restrict__ QV = base + (int64_t)kBufYS * n * n;  // v_k at QV[k n + i], tau_k at QV[(n-1) n + k]
   int Pr = 1;
   while (Pr < 4 && n * Pr * 2 <= NT) Pr *= 2;
   for (int k = 0; k + 2 < n; ++k) {
+    const int len = n - k - 1;
     double part = 0.0;
-    for (int i = k + 2 + tid; i < n; i += NT) part += HH(i, k) * HH(i, k);
-    const double sigma = block_sum(part, sred);
-    if (sigma == 0.0) continue;  // column already reduced (uniform decision)
+    for (int i = 1 + tid; i < len; i += NT) {
+      const double v = HH(k + 1 + i, k);
+      sv[i] = v;
+      part += v * v;
+    }
     const double x0 = HH(k + 1, k);
+    part = wave_sum(part);
+    double* red = sred + 4 * (k & 1);  // two reduction slots: no second barrier needed
+    if ((tid & 63) == 0) red[tid >> 6] = part;
+    __syncthreads();
+    double sigma = 0.0;
+    for (int w = 0; w < (NT + 63) / 64; ++w) sigma += red[w];
+    if (sigma == 0.0) {  // column already reduced (uniform decision)
+      if (tid == 0) QV[(int64_t)(n - 1) * n + k] = 0.0;
+      continue;
+    }
     const double nrm = sqrt(x0 * x0 + sigma);
     const double beta = (x0 >= 0.0) ? -nrm : nrm;
     const double tau = (beta - x0) / beta;
-    const double scal = 1.0 / (x0 - beta);
-    const int len = n - k - 1;
-    for (int i = tid; i < len; i += NT) sv[i] = (i == 0) ? 1.0 : HH(k + 1 + i, k) * scal;
-    __syncthreads();
-    for (int i = tid; i < len; i += NT) HH(k + 1 + i, k) = (i == 0) ? beta : 0.0;
+    const double dlt = x0 - beta;
+    const double scal = 1.0 / dlt;
+    for (int i = tid; i < len; i += NT) {
+      QV[(int64_t)k * n + i] = (i == 0) ? 1.0 : sv[i] * scal;
+      HH(k + 1 + i, k) = (i == 0) ? beta : 0.0;
+    }
+    if (tid == 0) QV[(int64_t)(n - 1) * n + k] = tau;
     // left: (I - tau v v^T) H on columns k+1..n-1
     int Pl = 1;
     while (Pl < 8 && len * Pl * 2 <= NT) Pl *= 2;
@@ -237,41 +257,35 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       const int c = c0 + tid / Pl;
       double w = 0.0;
       if (c < n) {
+        if (part_l == 0) w = HH(k + 1, c) * dlt;
 #pragma unroll 4
-        for (int i = part_l; i < len; i += Pl) w += sv[i] * HH(k + 1 + i, c);
+        for (int i = (part_l == 0 ? Pl : part_l); i < len; i += Pl) w += sv[i] * HH(k + 1 + i, c);
       }
       for (int o = 1; o < Pl; o <<= 1) w += __shfl_xor(w, o);
-      w *= tau;
+      w *= tau * scal;
       if (c < n) {
+        if (part_l == 0) HH(k + 1, c) -= w;
 #pragma unroll 4
-        for (int i = part_l; i < len; i += Pl) HH(k + 1 + i, c) -= sv[i] * w;
+        for (int i = (part_l == 0 ? Pl : part_l); i < len; i += Pl) HH(k + 1 + i, c) -= sv[i] * scal * w;
       }
     }
     __syncthreads();
-    // right: H (I - tau v v^T) and Z likewise, rows 0..n-1
+    // right: H (I - tau v v^T), rows 0..n-1
     const int part_r = tid & (Pr - 1);
     for (int r0 = 0; r0 < n; r0 += NT / Pr) {
       const int r = r0 + tid / Pr;
-      double y = 0.0, yz = 0.0;
+      double y = 0.0;
       if (r < n) {
+        if (part_r == 0) y = HH(r, k + 1);
 #pragma unroll 4
-        for (int i = part_r; i < len; i += Pr) {
-          y += HH(r, k + 1 + i) * sv[i];
-          yz += ZZ(r, k + 1 + i) * sv[i];
-        }
+        for (int i = (part_r == 0 ? Pr : part_r); i < len; i += Pr) y += HH(r, k + 1 + i) * (sv[i] * scal);
       }
-      for (int o = 1; o < Pr; o <<= 1) {
-        y += __shfl_xor(y, o);
-        yz += __shfl_xor(yz, o);
-      }
+      for (int o = 1; o < Pr; o <<= 1) y += __shfl_xor(y, o);
       y *= tau;
-      yz *= tau;
       if (r < n) {
+        if (part_r == 0) HH(r, k + 1) -= y;
 #pragma unroll 4
-        for (int i = part_r; i < len; i += Pr) {
-          HH(r, k + 1 + i) -= y * sv[i];
-          ZZ(r, k + 1 + i) -= yz * sv[i];
-        }
+        for (int i = (part_r == 0 ? Pr : part_r); i < len; i += Pr) HH(r, k + 1 + i) -= y * (sv[i] * scal);
       }
     }
     __syncthreads();
@@ -1037,6 +1051,47 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
     eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops);
   else
     eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops);
+}
+
+// U = Q U' for the reflectors of the Hessenberg reduction, Q = H_0 H_1 ... H_{n-3} with
+// H_k = I - tau_k v_k v_k^T on rows k+1..n-1 (v_k and tau_k left in the workspace by k_eigen):
+// U' = Z X from the QR phase becomes the eigenvector matrix of G. One workgroup per 16 columns;
+// the column block stays in LDS while the reflectors are applied from the last to the first.
+__global__ __launch_bounds__(256) void k_hqapply(const Item* items, double* ws, const int32_t* status) {
+  const Item it = items[blockIdx.y];
+  if (status[it.layer] != 0) return;
+  const int n = it.n;
+  const int c0 = blockIdx.x * 16;
+  if (c0 >= n) return;
+  double* base = ws + it.ws;
+  const double* __restrict__ QV = base + (int64_t)kBufYS * n * n;
+  const double* __restrict__ Up = base + (int64_t)kBufG * n * n;
+  double* __restrict__ U = base + (int64_t)kBufU * n * n;
+  __shared__ double sb[kMaxn * 17];  // rows x 16 columns, row stride 17
+  __shared__ double red[4][16];
+  const int tid = threadIdx.x, col = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
+  const int nc = min(16, n - c0);
+  for (int r = grp; r < n; r += ngrp) sb[r * 17 + col] = (col < nc) ? Up[(int64_t)r * n + c0 + col] : 0.0;
+  __syncthreads();
+  for (int k = n - 3; k >= 0; --k) {
+    const double tau = QV[(int64_t)(n - 1) * n + k];
+    if (tau == 0.0) continue;  // uniform
+    const double* v = QV + (int64_t)k * n;
+    const int len = n - k - 1;
+    double w = 0.0;
+    for (int i = grp; i < len; i += ngrp) w += v[i] * sb[(k + 1 + i) * 17 + col];
+    // the groups of one wave differ in lane bits 4 and 5
+    for (int o = 16; o < 64 && o < (int)blockDim.x; o <<= 1) w += __shfl_xor(w, o);
+    if ((tid & 63) < 16) red[tid >> 6][col] = w;
+    __syncthreads();
+    w = 0.0;
+    for (int q = 0; q < ((int)blockDim.x + 63) / 64; ++q) w += red[q][col];
+    w *= tau;
+    for (int i = grp; i < len; i += ngrp) sb[(k + 1 + i) * 17 + col] -= v[i] * w;
+    __syncthreads();
+  }
+  if (col < nc)
+    for (int r = grp; r < n; r += ngrp) U[(int64_t)r * n + c0 + col] = sb[r * 17 + col];
 }
 
 }  // namespace vbrdf

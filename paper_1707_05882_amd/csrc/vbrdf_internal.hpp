@@ -20,11 +20,11 @@ constexpr double kOmegaMax = 1.0 - 1e-12;
 enum Buf : int {
   kBufE = 0,   // E~ = M^-1 (I - omega/2 S+ W); later the emergent response R^m
   kBufF = 1,   // F~ = M^-1 (I - omega/2 S- W)
-  kBufG = 2,   // G = F~ E~ (eigen input; reduced in place when n > kLdsMaxn); later V = E~ U
+  kBufG = 2,   // G = F~ E~ (eigen input; reduced in place when n > kLdsMaxn); then U' = Z X; later V = E~ U
   kBufZ = 3,   // Schur vectors (column-major); later S' = U + V D_s
   kBufX = 4,   // eigenvectors of the quasi-triangular factor; later T' = U + V D_t
   kBufU = 5,   // eigenvectors U of G (columns)
-  kBufYS = 6,  // U S'^-1
+  kBufYS = 6,  // Householder vectors of the Hessenberg reduction; later U S'^-1
   kBufYT = 7,  // U T'^-1
   kNumBuf = 8
 };
@@ -73,6 +73,7 @@ __global__ void k_eigen(const Item* items, double* ws, int32_t* status);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
+__global__ void k_hqapply(const Item* items, double* ws, const int32_t* status);
 __global__ void k_lu(const Item* items, double* ws, int32_t* status);
 __global__ void k_trsm(const Item* items, double* ws, int32_t* status);
 // right-hand-side rows per right-division tile (one wave; n x (rows + 3) doubles of LDS)

@@ -183,6 +183,6 @@ def test_stage_timing():
     st = torch.empty(1, dtype=torch.int32, device=dev)
     plan.solve(t, w, c, F, st, torch.cuda.current_stream().cuda_stream)
     times = plan.stage_times()
-    assert list(times) == ["validate", "legendre", "assemble", "gemm_FE", "eigen", "gemm_U", "gemm_V", "vfix",
-                           "colscal", "bcbuild", "lu", "trsm", "response", "synth"]
+    assert list(times) == ["validate", "legendre", "assemble", "gemm_FE", "eigen", "gemm_U", "hqapply", "gemm_V",
+                           "vfix", "colscal", "bcbuild", "lu", "trsm", "response", "synth"]
     assert all(v >= 0 for v in times.values())
