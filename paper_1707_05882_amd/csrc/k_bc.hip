@@ -110,78 +110,69 @@ __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status) 
   }
 }
 
-__device__ inline void block_argmax(double v, int idx, double* sv, int* si) {
-  // leaves the winner in sv[0], si[0]; ties resolve to the smaller index
-  for (int o = 32; o > 0; o >>= 1) {
-    if (o < (int)blockDim.x) {
-      const double ov = __shfl_xor(v, o);
-      const int oi = __shfl_xor(idx, o);
-      if (ov > v || (ov == v && oi < idx)) {
-        v = ov;
-        idx = oi;
-      }
-    }
-  }
-  if ((threadIdx.x & 63) == 0) {
-    sv[threadIdx.x >> 6] = v;
-    si[threadIdx.x >> 6] = idx;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int w = 1; w < nw; ++w)
-      if (sv[w] > sv[0] || (sv[w] == sv[0] && si[w] < si[0])) {
-        sv[0] = sv[w];
-        si[0] = si[w];
-      }
-  }
-  __syncthreads();
-}
-
 // In-place LU factorisation with partial pivoting, P^T A = L Uu (row perm[k] of the original at
 // position k), unit L below the diagonal, invd[k] = 1 / Uu_kk. A has row stride ld and lives in LDS
 // or global memory (the caller passes a pointer derived from the __shared__ array so the accesses
 // compile to LDS instructions). Returns false (uniformly) on a zero or non-finite pivot.
+// Per column, wave 0 alone finds the pivot (largest modulus, ties to the smaller row), swaps the
+// rows and scales the column, lane-synchronous; then all waves apply the rank-1 update: two
+// workgroup barriers per column. The block size is a multiple of 64 (or below 64).
 __device__ __forceinline__ bool lu_factor(double* A, int64_t ld, int n, int* perm, double* invd, double* redv,
                                           int* redi) {
   const int tid = threadIdx.x, NT = blockDim.x;
+  const int W = NT < 64 ? NT : 64, lane = tid % W, wv = tid / W, nw = NT / W;
+  auto wsync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
   for (int i = tid; i < n; i += NT) perm[i] = i;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < n; i += NT) {
-      const double v = fabs(A[(int64_t)i * ld + k]);
-      if (v > best) {
-        best = v;
-        bi = i;
+    if (wv == 0) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + lane; i < n; i += W) {
+        const double v = fabs(A[(int64_t)i * ld + k]);
+        if (v > best || (v == best && i < bi)) {
+          best = v;
+          bi = i;
+        }
       }
-    }
-    block_argmax(best, bi, redv, redi);
-    const int p = redi[0];
-    const double pv = redv[0];
-    if (!(pv > 0.0) || !isfinite(pv)) return false;
-    if (p != k) {
-      for (int c = tid; c < n; c += NT) {
-        const double t = A[(int64_t)k * ld + c];
-        A[(int64_t)k * ld + c] = A[(int64_t)p * ld + c];
-        A[(int64_t)p * ld + c] = t;
+      for (int o = 32; o > 0; o >>= 1) {
+        if (o < W) {
+          const double ov = __shfl_xor(best, o);
+          const int oi = __shfl_xor(bi, o);
+          if (ov > best || (ov == best && oi < bi)) {
+            best = ov;
+            bi = oi;
+          }
+        }
       }
-      if (tid == 0) {
-        const int t = perm[k];
-        perm[k] = perm[p];
-        perm[p] = t;
+      const bool ok = best > 0.0 && isfinite(best);
+      if (ok && bi != k) {
+        for (int c = lane; c < n; c += W) {
+          const double t = A[(int64_t)k * ld + c];
+          A[(int64_t)k * ld + c] = A[(int64_t)bi * ld + c];
+          A[(int64_t)bi * ld + c] = t;
+        }
       }
+      wsync();
+      if (ok) {
+        const double inv = 1.0 / A[(int64_t)k * ld + k];
+        for (int i = k + 1 + lane; i < n; i += W) A[(int64_t)i * ld + k] *= inv;
+        if (lane == 0) {
+          invd[k] = inv;
+          const int t = perm[k];
+          perm[k] = perm[bi];
+          perm[bi] = t;
+        }
+      }
+      if (lane == 0) redi[k & 1] = ok ? 1 : 0;
     }
     __syncthreads();
-    const double inv = 1.0 / A[(int64_t)k * ld + k];
-    for (int i = k + 1 + tid; i < n; i += NT) A[(int64_t)i * ld + k] *= inv;
-    if (tid == 0) invd[k] = inv;
-    __syncthreads();
+    if (!redi[k & 1]) return false;
     // trailing update: lane l of wave w takes columns k+1+l, k+1+l+64, ... and rows k+1+w,
-    // k+1+w+nw, ... (no index division; A(i, k) is the same address for a whole wave). The
-    // block size is a multiple of 64 (or below 64).
-    const int W = NT < 64 ? NT : 64, lane = tid % W, wv = tid / W, nw = NT / W;
+    // k+1+w+nw, ... (no index division; A(i, k) is the same address for a whole wave)
     for (int c = k + 1 + lane; c < n; c += W) {
       const double akc = A[(int64_t)k * ld + c];
       for (int i = k + 1 + wv; i < n; i += nw) A[(int64_t)i * ld + c] -= A[(int64_t)i * ld + k] * akc;
@@ -307,11 +298,14 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int3
     if (own) {
       double a0 = b[j * ldb], a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int c = 0;
-      for (; c + 4 <= j; c += 4) {
-        a0 -= b[c * ldb] * col[c];
-        a1 -= b[(c + 1) * ldb] * col[c + 1];
-        a2 -= b[(c + 2) * ldb] * col[c + 2];
-        a3 -= b[(c + 3) * ldb] * col[c + 3];
+      for (; c + 16 <= j; c += 16) {
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) {
+          a0 -= b[(c + u) * ldb] * col[c + u];
+          a1 -= b[(c + u + 1) * ldb] * col[c + u + 1];
+          a2 -= b[(c + u + 2) * ldb] * col[c + u + 2];
+          a3 -= b[(c + u + 3) * ldb] * col[c + u + 3];
+        }
       }
       for (; c < j; ++c) a0 -= b[c * ldb] * col[c];
       b[j * ldb] = ((a0 + a1) + (a2 + a3)) * id[j];
@@ -330,11 +324,14 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int3
     if (own && j < n - 1) {
       double a0 = b[j * ldb], a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int c = j + 1;
-      for (; c + 4 <= n; c += 4) {
-        a0 -= b[c * ldb] * col[c];
-        a1 -= b[(c + 1) * ldb] * col[c + 1];
-        a2 -= b[(c + 2) * ldb] * col[c + 2];
-        a3 -= b[(c + 3) * ldb] * col[c + 3];
+      for (; c + 16 <= n; c += 16) {
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) {
+          a0 -= b[(c + u) * ldb] * col[c + u];
+          a1 -= b[(c + u + 1) * ldb] * col[c + u + 1];
+          a2 -= b[(c + u + 2) * ldb] * col[c + u + 2];
+          a3 -= b[(c + u + 3) * ldb] * col[c + u + 3];
+        }
       }
       for (; c < n; ++c) a0 -= b[c * ldb] * col[c];
       b[j * ldb] = (a0 + a1) + (a2 + a3);

@@ -1055,11 +1055,12 @@ __global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, in
 
 // U = Q U' for the reflectors of the Hessenberg reduction, Q = H_0 H_1 ... H_{n-3} with
 // H_k = I - tau_k v_k v_k^T on rows k+1..n-1 (v_k and tau_k left in the workspace by k_eigen):
-// U' = Z X from the QR phase becomes the eigenvector matrix of G. One workgroup per 16 columns;
-// the column block stays in LDS while the reflectors are applied from the last to the first.
-__global__ __launch_bounds__(256) void k_hqapply(const Item* items, double* ws, const int32_t* status) {
-  const Item it = items[blockIdx.y];
-  if (status[it.layer] != 0) return;
+// U' = Z X from the QR phase becomes the eigenvector matrix of G. One workgroup of 256 threads
+// (16 row groups x 16 columns) per 16 columns; the column block stays in LDS while the reflectors
+// are applied from the last to the first, each thread's entries of the next reflector (kPer of
+// them, rows i = group + 16 q) loaded while the current one is applied.
+template <int kPer>
+__device__ __forceinline__ void hqapply_body(const Item& it, double* ws, double* sb, double (*red)[16]) {
   const int n = it.n;
   const int c0 = blockIdx.x * 16;
   if (c0 >= n) return;
@@ -1067,31 +1068,71 @@ __global__ __launch_bounds__(256) void k_hqapply(const Item* items, double* ws, 
   const double* __restrict__ QV = base + (int64_t)kBufYS * n * n;
   const double* __restrict__ Up = base + (int64_t)kBufG * n * n;
   double* __restrict__ U = base + (int64_t)kBufU * n * n;
-  __shared__ double sb[kMaxn * 17];  // rows x 16 columns, row stride 17
-  __shared__ double red[4][16];
-  const int tid = threadIdx.x, col = tid & 15, grp = tid >> 4, ngrp = blockDim.x >> 4;
+  constexpr int ngrp = 16;
+  const int tid = threadIdx.x, col = tid & 15, grp = tid >> 4;
   const int nc = min(16, n - c0);
   for (int r = grp; r < n; r += ngrp) sb[r * 17 + col] = (col < nc) ? Up[(int64_t)r * n + c0 + col] : 0.0;
+  double vc[kPer], vn[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) vc[q] = vn[q] = 0.0;
+  double tau_n = 0.0;
+  if (n >= 3) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = grp + ngrp * q;
+      if (i < 2) vn[q] = QV[(int64_t)(n - 3) * n + i];
+    }
+    tau_n = QV[(int64_t)(n - 1) * n + n - 3];
+  }
   __syncthreads();
   for (int k = n - 3; k >= 0; --k) {
-    const double tau = QV[(int64_t)(n - 1) * n + k];
-    if (tau == 0.0) continue;  // uniform
-    const double* v = QV + (int64_t)k * n;
+    const double tau = tau_n;
     const int len = n - k - 1;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) vc[q] = vn[q];
+    if (k > 0) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int i = grp + ngrp * q;
+        vn[q] = (i < len + 1) ? QV[(int64_t)(k - 1) * n + i] : 0.0;
+      }
+      tau_n = QV[(int64_t)(n - 1) * n + k - 1];
+    }
+    if (tau == 0.0) continue;  // uniform
     double w = 0.0;
-    for (int i = grp; i < len; i += ngrp) w += v[i] * sb[(k + 1 + i) * 17 + col];
-    // the groups of one wave differ in lane bits 4 and 5
-    for (int o = 16; o < 64 && o < (int)blockDim.x; o <<= 1) w += __shfl_xor(w, o);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = grp + ngrp * q;
+      if (i < len) w += vc[q] * sb[(k + 1 + i) * 17 + col];
+    }
+    // the row groups of one wave differ in lane bits 4 and 5
+    w += __shfl_xor(w, 16);
+    w += __shfl_xor(w, 32);
     if ((tid & 63) < 16) red[tid >> 6][col] = w;
     __syncthreads();
-    w = 0.0;
-    for (int q = 0; q < ((int)blockDim.x + 63) / 64; ++q) w += red[q][col];
-    w *= tau;
-    for (int i = grp; i < len; i += ngrp) sb[(k + 1 + i) * 17 + col] -= v[i] * w;
+    w = (red[0][col] + red[1][col] + red[2][col] + red[3][col]) * tau;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = grp + ngrp * q;
+      if (i < len) sb[(k + 1 + i) * 17 + col] -= vc[q] * w;
+    }
     __syncthreads();
   }
   if (col < nc)
     for (int r = grp; r < n; r += ngrp) U[(int64_t)r * n + c0 + col] = sb[r * 17 + col];
+}
+
+__global__ __launch_bounds__(256) void k_hqapply(const Item* items, double* ws, const int32_t* status) {
+  const Item it = items[blockIdx.y];
+  if (status[it.layer] != 0) return;
+  __shared__ double sb[kMaxn * 17];  // rows x 16 columns, row stride 17
+  __shared__ double red[4][16];
+  if (it.n <= 128)
+    hqapply_body<8>(it, ws, sb, red);
+  else if (it.n <= 256)
+    hqapply_body<16>(it, ws, sb, red);
+  else
+    hqapply_body<32>(it, ws, sb, red);
 }
 
 }  // namespace vbrdf
