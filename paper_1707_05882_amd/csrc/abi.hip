@@ -199,8 +199,8 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     for (int i = 0; i < ly.N; ++i)
       for (int q = 0; q < ly.N; ++q) tasks.push_back(SynthTask{l, i, q, 0});
     p->max_n = std::max(p->max_n, n);
-    p->trsm_tiles = std::max(p->trsm_tiles, (n + trsm_rows(n) - 1) / trsm_rows(n));
-    p->trsm_lds = std::max(p->trsm_lds, sizeof(double) * (size_t)n * (trsm_rows(n) + 3));
+    p->trsm_tiles = std::max(p->trsm_tiles, (n + kTrsmRows - 1) / kTrsmRows);
+    p->trsm_lds = std::max(p->trsm_lds, sizeof(double) * (size_t)n * (kTrsmRows + 3));
     p->max_N = std::max(p->max_N, ly.N);
     coef_off += 6 * (int64_t)ly.L;
     out_off += (int64_t)ly.N * ly.N * ly.n_dphi * 16;

@@ -237,16 +237,18 @@ __global__ __launch_bounds__(256) void k_lu(const Item* items, double* ws, int32
 }
 
 // Right division Y = U A^-1 with the factors of k_lu, for S' and T' (blockIdx.y) and a tile of
-// R rows of U (blockIdx.x). One wave; lane r owns row r of the tile, kept in LDS as Bt[c][r]
-// (row stride R + 1), and solves it on its own: no workgroup barrier. With W = Y P:
+// 16 rows of U (blockIdx.x). One wave: four lanes share a row (lane = 4 row + part), each taking
+// every fourth term of the row's dot products, combined by two lane exchanges. The tile is kept
+// in LDS as Bt[c][r] (row stride 17). No workgroup barrier. With W = Y P:
 //   Z Uu = U :  Z_j = (U_j - sum_{c<j} Z_c Uu_cj) / Uu_jj      (j ascending)
 //   W L = Z  :  W_j = Z_j - sum_{c>j} W_c L_cj                 (j descending, unit L)
-// and Y[:, perm[j]] = W[:, j]. The factor entries are the same for all lanes.
+// and Y[:, perm[j]] = W[:, j]. The factor column used at step j is the same for all rows: the
+// wave stages it in LDS while the loads of the next column are in flight.
 __global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int32_t* status) {
   const Item it = items[blockIdx.z];
   if (status[it.layer] != 0) return;
   const int n = it.n, lane = threadIdx.x;
-  const int R = trsm_rows(n);
+  constexpr int R = kTrsmRows;
   const int r0 = blockIdx.x * R;
   if (r0 >= n) return;
   const int which = blockIdx.y;
@@ -257,16 +259,16 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int3
   double* ex = base + extras_off(n);
   const double* __restrict__ id = lu_invd(ex, n, which);
   const int* __restrict__ pm = lu_perm(ex, n, which);
-  // LDS: Bt [n][R + 1] (lane r's row of the tile down column r), then two factor-column buffers
+  // LDS: Bt [n][R + 1], then two factor-column buffers [2][n]
   HIP_DYNAMIC_SHARED(double, smem)
-  const int ldb = R + 1;
+  constexpr int ldb = R + 1;
   double* Bt = smem;
-  double* cb = smem + (int64_t)n * ldb;  // [2][n]
+  double* cb = smem + (int64_t)n * ldb;
   const int nr = min(R, n - r0);
-  for (int rr = 0; rr < nr; ++rr)
-    for (int c = lane; c < n; c += 64) Bt[c * ldb + rr] = U[(int64_t)(r0 + rr) * n + c];
-  // Each step j reads factor column j from LDS (the same address in all lanes) while the wave's
-  // loads of the next column are in flight.
+  for (int t = lane; t < nr * n; t += 64) {
+    const int rr = t / n, c = t % n;
+    Bt[c * ldb + rr] = U[(int64_t)(r0 + rr) * n + c];
+  }
   double pre[kMaxn / 64];
   auto fetch = [&](int j) {
 #pragma unroll
@@ -286,8 +288,9 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int3
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   };
-  double* b = Bt + lane;
-  const bool own = lane < nr;
+  const int row = lane >> 2, part = lane & 3;
+  double* b = Bt + row;
+  const bool own = row < nr;
   // Z Uu = U, j ascending
   fetch(0);
   stash(cb);
@@ -295,22 +298,18 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int3
   for (int j = 0; j < n; ++j) {
     const double* col = cb + (j & 1) * n;
     if (j + 1 < n) fetch(j + 1);
-    if (own) {
-      double a0 = b[j * ldb], a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int c = 0;
-      for (; c + 16 <= j; c += 16) {
-#pragma unroll
-        for (int u = 0; u < 16; u += 4) {
-          a0 -= b[(c + u) * ldb] * col[c + u];
-          a1 -= b[(c + u + 1) * ldb] * col[c + u + 1];
-          a2 -= b[(c + u + 2) * ldb] * col[c + u + 2];
-          a3 -= b[(c + u + 3) * ldb] * col[c + u + 3];
-        }
-      }
-      for (; c < j; ++c) a0 -= b[c * ldb] * col[c];
-      b[j * ldb] = ((a0 + a1) + (a2 + a3)) * id[j];
+    double a0 = 0.0, a1 = 0.0;
+    int c = part;
+    for (; c + 4 < j; c += 8) {
+      a0 -= b[c * ldb] * col[c];
+      a1 -= b[(c + 4) * ldb] * col[c + 4];
     }
-    sync();  // every lane is done with the buffer the next stash overwrites
+    if (c < j) a0 -= b[c * ldb] * col[c];
+    double acc = a0 + a1;
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (own && part == 0) b[j * ldb] = (b[j * ldb] + acc) * id[j];
+    sync();  // the new entry and every read of the buffer the next stash overwrites are done
     if (j + 1 < n) stash(cb + ((j + 1) & 1) * n);
     sync();
   }
@@ -321,27 +320,25 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int3
   for (int j = n - 1; j >= 0; --j) {
     const double* col = cb + (j & 1) * n;
     if (j > 0) fetch(j - 1);
-    if (own && j < n - 1) {
-      double a0 = b[j * ldb], a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int c = j + 1;
-      for (; c + 16 <= n; c += 16) {
-#pragma unroll
-        for (int u = 0; u < 16; u += 4) {
-          a0 -= b[(c + u) * ldb] * col[c + u];
-          a1 -= b[(c + u + 1) * ldb] * col[c + u + 1];
-          a2 -= b[(c + u + 2) * ldb] * col[c + u + 2];
-          a3 -= b[(c + u + 3) * ldb] * col[c + u + 3];
-        }
-      }
-      for (; c < n; ++c) a0 -= b[c * ldb] * col[c];
-      b[j * ldb] = (a0 + a1) + (a2 + a3);
+    double a0 = 0.0, a1 = 0.0;
+    int c = j + 1 + part;
+    for (; c + 4 < n; c += 8) {
+      a0 -= b[c * ldb] * col[c];
+      a1 -= b[(c + 4) * ldb] * col[c + 4];
     }
+    if (c < n) a0 -= b[c * ldb] * col[c];
+    double acc = a0 + a1;
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (own && part == 0) b[j * ldb] += acc;
     sync();
     if (j > 0) stash(cb + ((j - 1) & 1) * n);
     sync();
   }
-  for (int rr = 0; rr < nr; ++rr)
-    for (int c = lane; c < n; c += 64) Y[(int64_t)(r0 + rr) * n + pm[c]] = Bt[c * ldb + rr];
+  for (int t = lane; t < nr * n; t += 64) {
+    const int rr = t / n, c = t % n;
+    Y[(int64_t)(r0 + rr) * n + pm[c]] = Bt[c * ldb + rr];
+  }
 }
 
 // Columns of V = E~ U that lost more than ~7 digits to cancellation (the conservation mode of

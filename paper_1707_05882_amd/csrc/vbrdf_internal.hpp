@@ -76,8 +76,9 @@ __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
 __global__ void k_hqapply(const Item* items, double* ws, const int32_t* status);
 __global__ void k_lu(const Item* items, double* ws, int32_t* status);
 __global__ void k_trsm(const Item* items, double* ws, int32_t* status);
-// right-hand-side rows per right-division tile (one wave; n x (rows + 3) doubles of LDS)
-__host__ __device__ inline int trsm_rows(int n) { return n <= 256 ? 64 : 32; }
+// right-hand-side rows per right-division tile (one wave, four lanes per row; the tile takes
+// n x (kTrsmRows + 3) doubles of LDS)
+constexpr int kTrsmRows = 16;
 __global__ void k_response(const Item* items, const Layer* layers, const double* quad, double* ws,
                            const int32_t* status);
 __global__ void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
