@@ -917,32 +917,176 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     return;
   }
 
-  // ---- 3. eigenvectors of the quasi-triangular factor by back-substitution
+  // ---- 3. eigenvectors of the quasi-triangular factor T by back-substitution. Eigenvalues
+  // closer than a few ulp ||G|| cannot be told apart: a diagonal entry (or 2x2 block) that close to
+  // lambda is another copy of the same multiple eigenvalue of a diagonalisable matrix (e.g. the
+  // unscattered Stokes components at one node, lambda = 1/mu^2), and its Schur coupling is
+  // rounding noise. Its component is set to zero instead of dividing the noise by a guarded pivot,
+  // which would make the copies' eigenvectors parallel.
+  const double same = 8.0 * kUlp * hnorm;
+  if constexpr (kLds) {
+    // All eigenvectors advance together over T's diagonal blocks from the bottom: the block's
+    // rows of T are staged in LDS (the same for every thread) and the eigenvector matrix X
+    // replaces T in the LDS array, so every dependent read stays in LDS. T itself goes to the
+    // workspace first.
+    double* TG = base + (int64_t)kBufYT * n * n;
+    for (int t = tid; t < n * n; t += NT) TG[t] = HH(t / n, t % n);
+    __syncthreads();
+    double* X = sH;  // X(i, j) at X[i * ld + j]
+    double* trow = srefl;  // rows s and i of the current block: [2][n]
+    for (int t = tid; t < n * ld; t += NT) X[t] = 0.0;
+    __syncthreads();
+    // own blocks (the rest of each column stays zero below them)
+    for (int j = tid; j < n; j += NT) {
+      const double wr = lre[j], wi = lim[j];
+      if (wi < 0.0) continue;  // second member of a complex pair: written by j - 1
+      const int b0 = (blk[j] == 0) ? j - 1 : j;
+      const int bend = (blk[b0] == 2) ? b0 + 1 : b0;
+      const bool cplx = wi > 0.0;
+      const Cx lam{wr, wi};
+      Cx xb0{0.0, 0.0}, xb1{0.0, 0.0};
+      if (bend == b0) {
+        xb0 = {1.0, 0.0};
+      } else {
+        const Cx a{TG[(int64_t)b0 * n + b0], 0.0}, bb{TG[(int64_t)b0 * n + b0 + 1], 0.0};
+        const Cx c{TG[(int64_t)(b0 + 1) * n + b0], 0.0}, d{TG[(int64_t)(b0 + 1) * n + b0 + 1], 0.0};
+        const Cx v0a = bb, v1a = csub(lam, a);  // (b, lambda - a)
+        const Cx v0b = csub(lam, d), v1b = c;   // (lambda - d, c)
+        if (cabs1(v0a) + cabs1(v1a) >= cabs1(v0b) + cabs1(v1b)) {
+          xb0 = v0a;
+          xb1 = v1a;
+        } else {
+          xb0 = v0b;
+          xb1 = v1b;
+        }
+        if (cabs1(xb0) + cabs1(xb1) == 0.0) {
+          if (j == b0) xb0 = {1.0, 0.0}; else xb1 = {1.0, 0.0};
+        }
+      }
+      X[b0 * ld + j] = xb0.re;
+      if (cplx) X[b0 * ld + j + 1] = xb0.im;
+      if (bend > b0) {
+        X[bend * ld + j] = xb1.re;
+        if (cplx) X[bend * ld + j + 1] = xb1.im;
+      }
+    }
+    for (int i = n - 1; i >= 0;) {
+      const int sb = (blk[i] == 0) ? i - 1 : i;  // block rows [sb, i]
+      __syncthreads();  // previous block's rows are no longer read
+      for (int c = tid; c < n; c += NT) {
+        trow[c] = TG[(int64_t)sb * n + c];
+        trow[n + c] = TG[(int64_t)i * n + c];
+      }
+      __syncthreads();
+      for (int j = tid; j < n; j += NT) {
+        const double wr = lre[j], wi = lim[j];
+        if (wi < 0.0) continue;
+        const int b0 = (blk[j] == 0) ? j - 1 : j;
+        if (i >= b0) continue;  // this block is not above the eigenvector's own block
+        const int bend = (blk[b0] == 2) ? b0 + 1 : b0;
+        const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
+        const bool cplx = wi > 0.0;
+        const Cx lam{wr, wi};
+        const double* ts = trow;
+        const double* ti = trow + n;
+        Cx r0{0.0, 0.0}, r1{0.0, 0.0};
+        if (cplx) {
+          for (int c = i + 1; c <= bend; ++c) {
+            const double xr = X[c * ld + j], xi = X[c * ld + j + 1];
+            r0.re -= ts[c] * xr;
+            r0.im -= ts[c] * xi;
+            if (sb < i) {
+              r1.re -= ti[c] * xr;
+              r1.im -= ti[c] * xi;
+            }
+          }
+        } else if (sb == i) {
+          double a0 = 0.0, a1 = 0.0;
+          int c = i + 1;
+          for (; c + 1 <= bend; c += 2) {
+            a0 -= ts[c] * X[c * ld + j];
+            a1 -= ts[c + 1] * X[(c + 1) * ld + j];
+          }
+          if (c <= bend) a0 -= ts[c] * X[c * ld + j];
+          r0.re = a0 + a1;
+        } else {
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll 4
+          for (int c = i + 1; c <= bend; ++c) {
+            const double xc = X[c * ld + j];
+            a0 -= ts[c] * xc;
+            a1 -= ti[c] * xc;
+          }
+          r0.re = a0;
+          r1.re = a1;
+        }
+        if (sb == i) {
+          const Cx d0 = csub(Cx{ti[i], 0.0}, lam);
+          const Cx xi = (cabs1(d0) <= same) ? Cx{0.0, 0.0} : cdiv(r0, cguard(d0, smin));
+          X[i * ld + j] = xi.re;
+          if (cplx) X[i * ld + j + 1] = xi.im;
+        } else if (cabs1(csub(Cx{lre[sb], lim[sb]}, lam)) <= same || cabs1(csub(Cx{lre[i], lim[i]}, lam)) <= same) {
+          X[sb * ld + j] = 0.0;
+          X[i * ld + j] = 0.0;
+          if (cplx) {
+            X[sb * ld + j + 1] = 0.0;
+            X[i * ld + j + 1] = 0.0;
+          }
+        } else {
+          Cx x0, x1;
+          csolve2(csub(Cx{ts[sb], 0.0}, lam), Cx{ts[i], 0.0}, Cx{ti[sb], 0.0}, csub(Cx{ti[i], 0.0}, lam), r0, r1,
+                  smin, x0, x1);
+          X[sb * ld + j] = x0.re;
+          X[i * ld + j] = x1.re;
+          if (cplx) {
+            X[sb * ld + j + 1] = x0.im;
+            X[i * ld + j + 1] = x1.im;
+          }
+        }
+      }
+      i = sb - 1;
+    }
+    __syncthreads();
+    // normalise (max modulus component -> 1) and write out
+    for (int j = tid; j < n; j += NT) {
+      const double wi = lim[j];
+      if (wi < 0.0) continue;
+      const bool cplx = wi > 0.0;
+      double mx = 0.0;
+      for (int q = 0; q < n; ++q) {
+        double v = fabs(X[q * ld + j]);
+        if (cplx) v += fabs(X[q * ld + j + 1]);
+        mx = fmax(mx, v);
+      }
+      const double sc = (mx > 0.0) ? 1.0 / mx : 1.0;
+      for (int q = 0; q < n; ++q) {
+        X[q * ld + j] *= sc;
+        if (cplx) X[q * ld + j + 1] *= sc;
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < n * n; t += NT) XT[t] = X[(t / n) * ld + (t % n)];
+  } else {
+#define TV(r, c) H[(int64_t)(r) * ld + (c)]
+#define XV(r, c) XT[(int64_t)(r) * n + (c)]
   for (int j = tid; j < n; j += NT) {
     const double wr = lre[j], wi = lim[j];
     if (wi < 0.0) continue;  // second member of a complex pair: written by j - 1
     const int b0 = (blk[j] == 0) ? j - 1 : j;   // own block start
     const int bend = (blk[b0] == 2) ? b0 + 1 : b0;
     const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
-    // Eigenvalues closer than a few ulp ||G|| cannot be told apart: a diagonal entry (or 2x2
-    // block) that close to lambda is another copy of the same multiple eigenvalue of a
-    // diagonalisable matrix (e.g. the unscattered Stokes components at one node,
-    // lambda = 1/mu^2), and its Schur coupling is rounding noise. Its component is set to zero
-    // instead of dividing the noise by a guarded pivot, which would make the copies' eigenvectors
-    // parallel.
-    const double same = 8.0 * kUlp * hnorm;
     const bool cplx = wi > 0.0;
     const Cx lam{wr, wi};
     for (int i = bend + 1; i < n; ++i) {
-      XT[(int64_t)i * n + j] = 0.0;
-      if (cplx) XT[(int64_t)i * n + j + 1] = 0.0;
+      XV(i, j) = 0.0;
+      if (cplx) XV(i, j + 1) = 0.0;
     }
     // own block
     Cx xb0{0.0, 0.0}, xb1{0.0, 0.0};
     if (bend == b0) {
       xb0 = {1.0, 0.0};
     } else {
-      const Cx a{HH(b0, b0), 0.0}, bb{HH(b0, b0 + 1), 0.0}, c{HH(b0 + 1, b0), 0.0}, d{HH(b0 + 1, b0 + 1), 0.0};
+      const Cx a{TV(b0, b0), 0.0}, bb{TV(b0, b0 + 1), 0.0}, c{TV(b0 + 1, b0), 0.0}, d{TV(b0 + 1, b0 + 1), 0.0};
       const Cx v0a = bb, v1a = csub(lam, a);   // (b, lambda - a)
       const Cx v0b = csub(lam, d), v1b = c;    // (lambda - d, c)
       if (cabs1(v0a) + cabs1(v1a) >= cabs1(v0b) + cabs1(v1b)) {
@@ -956,11 +1100,11 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
         if (j == b0) xb0 = {1.0, 0.0}; else xb1 = {1.0, 0.0};
       }
     }
-    XT[(int64_t)b0 * n + j] = xb0.re;
-    if (cplx) XT[(int64_t)b0 * n + j + 1] = xb0.im;
+    XV(b0, j) = xb0.re;
+    if (cplx) XV(b0, j + 1) = xb0.im;
     if (bend > b0) {
-      XT[(int64_t)bend * n + j] = xb1.re;
-      if (cplx) XT[(int64_t)bend * n + j + 1] = xb1.im;
+      XV(bend, j) = xb1.re;
+      if (cplx) XV(bend, j + 1) = xb1.im;
     }
     // blocks above, bottom to top
     int i = b0 - 1;
@@ -969,12 +1113,12 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       Cx r0{0.0, 0.0}, r1{0.0, 0.0};
       if (cplx) {
         for (int c = i + 1; c <= bend; ++c) {
-          const double xr = XT[(int64_t)c * n + j], xi = XT[(int64_t)c * n + j + 1];
-          const double t0 = HH(s, c);
+          const double xr = XV(c, j), xi = XV(c, j + 1);
+          const double t0 = TV(s, c);
           r0.re -= t0 * xr;
           r0.im -= t0 * xi;
           if (s < i) {
-            const double t1 = HH(i, c);
+            const double t1 = TV(i, c);
             r1.re -= t1 * xr;
             r1.im -= t1 * xi;
           }
@@ -982,40 +1126,40 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       } else if (s == i) {
         double acc = 0.0;
 #pragma unroll 8
-        for (int c = i + 1; c <= bend; ++c) acc -= HH(s, c) * XT[(int64_t)c * n + j];
+        for (int c = i + 1; c <= bend; ++c) acc -= TV(s, c) * XV(c, j);
         r0.re = acc;
       } else {
         double a0 = 0.0, a1 = 0.0;
 #pragma unroll 4
         for (int c = i + 1; c <= bend; ++c) {
-          const double xc = XT[(int64_t)c * n + j];
-          a0 -= HH(s, c) * xc;
-          a1 -= HH(i, c) * xc;
+          const double xc = XV(c, j);
+          a0 -= TV(s, c) * xc;
+          a1 -= TV(i, c) * xc;
         }
         r0.re = a0;
         r1.re = a1;
       }
       if (s == i) {
-        const Cx d0 = csub(Cx{HH(i, i), 0.0}, lam);
+        const Cx d0 = csub(Cx{TV(i, i), 0.0}, lam);
         const Cx xi = (cabs1(d0) <= same) ? Cx{0.0, 0.0} : cdiv(r0, cguard(d0, smin));
-        XT[(int64_t)i * n + j] = xi.re;
-        if (cplx) XT[(int64_t)i * n + j + 1] = xi.im;
+        XV(i, j) = xi.re;
+        if (cplx) XV(i, j + 1) = xi.im;
       } else if (cabs1(csub(Cx{lre[s], lim[s]}, lam)) <= same || cabs1(csub(Cx{lre[i], lim[i]}, lam)) <= same) {
-        XT[(int64_t)s * n + j] = 0.0;
-        XT[(int64_t)i * n + j] = 0.0;
+        XV(s, j) = 0.0;
+        XV(i, j) = 0.0;
         if (cplx) {
-          XT[(int64_t)s * n + j + 1] = 0.0;
-          XT[(int64_t)i * n + j + 1] = 0.0;
+          XV(s, j + 1) = 0.0;
+          XV(i, j + 1) = 0.0;
         }
       } else {
         Cx x0, x1;
-        csolve2(csub(Cx{HH(s, s), 0.0}, lam), Cx{HH(s, i), 0.0}, Cx{HH(i, s), 0.0},
-                csub(Cx{HH(i, i), 0.0}, lam), r0, r1, smin, x0, x1);
-        XT[(int64_t)s * n + j] = x0.re;
-        XT[(int64_t)i * n + j] = x1.re;
+        csolve2(csub(Cx{TV(s, s), 0.0}, lam), Cx{TV(s, i), 0.0}, Cx{TV(i, s), 0.0},
+                csub(Cx{TV(i, i), 0.0}, lam), r0, r1, smin, x0, x1);
+        XV(s, j) = x0.re;
+        XV(i, j) = x1.re;
         if (cplx) {
-          XT[(int64_t)s * n + j + 1] = x0.im;
-          XT[(int64_t)i * n + j + 1] = x1.im;
+          XV(s, j + 1) = x0.im;
+          XV(i, j + 1) = x1.im;
         }
       }
       i = s - 1;
@@ -1023,15 +1167,18 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     // normalise (max modulus component -> 1)
     double mx = 0.0;
     for (int q = 0; q <= bend; ++q) {
-      double v = fabs(XT[(int64_t)q * n + j]);
-      if (cplx) v += fabs(XT[(int64_t)q * n + j + 1]);
+      double v = fabs(XV(q, j));
+      if (cplx) v += fabs(XV(q, j + 1));
       mx = fmax(mx, v);
     }
     const double sc = (mx > 0.0) ? 1.0 / mx : 1.0;
     for (int q = 0; q <= bend; ++q) {
-      XT[(int64_t)q * n + j] *= sc;
-      if (cplx) XT[(int64_t)q * n + j + 1] *= sc;
+      XV(q, j) *= sc;
+      if (cplx) XV(q, j + 1) *= sc;
     }
+  }
+#undef TV
+#undef XV
   }
 #undef HH
 #undef ZZ
