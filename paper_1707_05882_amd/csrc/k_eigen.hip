@@ -970,13 +970,35 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
         if (cplx) X[bend * ld + j + 1] = xb1.im;
       }
     }
+    // the next block's rows are loaded into registers while the current block is solved
+    double ps[4], pi[4];
+    auto fetch_rows = [&](int sbq, int iq) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = tid + q * NT;
+        if (c < n) {
+          ps[q] = TG[(int64_t)sbq * n + c];
+          pi[q] = TG[(int64_t)iq * n + c];
+        }
+      }
+    };
+    fetch_rows((blk[n - 1] == 0) ? n - 2 : n - 1, n - 1);
     for (int i = n - 1; i >= 0;) {
       const int sb = (blk[i] == 0) ? i - 1 : i;  // block rows [sb, i]
       __syncthreads();  // previous block's rows are no longer read
-      for (int c = tid; c < n; c += NT) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = tid + q * NT;
+        if (c < n) {
+          trow[c] = ps[q];
+          trow[n + c] = pi[q];
+        }
+      }
+      for (int c = tid + 4 * NT; c < n; c += NT) {  // only with fewer than n / 4 threads
         trow[c] = TG[(int64_t)sb * n + c];
         trow[n + c] = TG[(int64_t)i * n + c];
       }
+      if (sb > 0) fetch_rows((blk[sb - 1] == 0) ? sb - 2 : sb - 1, sb - 1);
       __syncthreads();
       for (int j = tid; j < n; j += NT) {
         const double wr = lre[j], wi = lim[j];
