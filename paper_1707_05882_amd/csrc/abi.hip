@@ -285,7 +285,7 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
   const dim3 gg(gt, gt, ni);
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, 0, kBufE, kBufG, layer_status);  // G = F~ E~
   mark();
-  k_eigen<<<ni, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufG, layer_status);  // U' = Z X
   mark();

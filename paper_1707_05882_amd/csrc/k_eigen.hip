@@ -109,6 +109,7 @@ enum : int { kActDeflated = 0, kActSweep = 1, kActRotate = 2, kActStop = 3, kAct
 constexpr int kMultiMin = 32;
 constexpr int kMultiIts = 6;
 constexpr int kMultiGap = 4;
+constexpr int kMaxBulges = kEigenThreads / 64;  // one bulge per wave
 
 // Z-update descriptor of one QR iteration, produced by wave 0 and applied by the other waves
 // during the next iteration (double-buffered): kind 0 none, 1 sweep (reflectors of steps lo..hh-1
@@ -230,7 +231,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     }
     const double x0 = HH(k + 1, k);
     part = wave_sum(part);
-    double* red = sred + 4 * (k & 1);  // two reduction slots: no second barrier needed
+    double* red = sred + 8 * (k & 1);  // two reduction slots: no second barrier needed
     if ((tid & 63) == 0) red[tid >> 6] = part;
     __syncthreads();
     double sigma = 0.0;
@@ -385,7 +386,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
             } else if (nwave >= 2 && its < kMultiIts && hh - l + 1 >= kMultiMin) {
               // one shift pair per bulge: the eigenvalues of the 2x2 diagonal blocks ending at
               // rows hh, hh - 2, ... (both roots of a real pair), stored in this slot's buffer
-              const int nb = nwave < 4 ? nwave : 4;
+              const int nb = nwave < kMaxBulges ? nwave : kMaxBulges;
               for (int bq = 0; bq < nb; ++bq) {
                 const int j = hh - 2 * bq;
                 const double a = HH(j - 1, j - 1), b = HH(j - 1, j), c = HH(j, j - 1), d = HH(j, j);
@@ -1206,12 +1207,12 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
 #undef ZZ
 }
 
-__global__ __launch_bounds__(256) void k_eigen(const Item* items, double* ws, int32_t* status) {
+__global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, double* ws, int32_t* status) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
   __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1) + 3 * 64];
   __shared__ double srefl[2 * 3 * kMaxn];
-  __shared__ double sred[8];
+  __shared__ double sred[16];
   __shared__ int sctl[8];
   __shared__ double sxyz[3];
   __shared__ ZOp zops[2];

@@ -13,6 +13,7 @@ namespace vbrdf {
 
 constexpr int kMaxN = 128;          // nodes per hemisphere
 constexpr int kMaxn = 4 * kMaxN;     // Stokes system size 4N
+constexpr int kEigenThreads = 512;  // k_eigen workgroup: 8 waves
 constexpr int kLdsMaxn = 128;        // largest system kept whole in LDS (128 x 129 doubles)
 constexpr double kOmegaMax = 1.0 - 1e-12;
 
