@@ -56,6 +56,10 @@ typedef int32_t vbrdf_status;
 
 /* Plan flags. */
 #define VBRDF_FLAG_STAGE_TIMING 1 /* record a hipEvent between the stages of every solve */
+/* Capture the launch sequence of vbrdf_solve into a hipGraph on first use and replay it; the graph
+ * is captured again whenever the device pointers or the stream of a call differ from the previous
+ * call's. Needs a non-default stream; cannot be combined with VBRDF_FLAG_STAGE_TIMING. */
+#define VBRDF_FLAG_GRAPH 2
 
 /* Largest supported quadrature order per hemisphere (Stokes system size 4N = 512). */
 #define VBRDF_MAX_N 128
@@ -70,7 +74,7 @@ typedef struct vbrdf_plan_desc {
   const int32_t* M;          /* host [n_layers]: Fourier orders m = 0..M-1, 1 <= M <= L */
   const int32_t* n_dphi;     /* host [n_layers]: azimuth samples, >= 1 */
   int32_t precision;         /* VBRDF_PRECISION_FP64 */
-  int32_t flags;             /* 0 or VBRDF_FLAG_STAGE_TIMING */
+  int32_t flags;             /* 0, VBRDF_FLAG_STAGE_TIMING or VBRDF_FLAG_GRAPH */
   uint64_t workspace_cap_bytes; /* 0 = no cap; otherwise plan creation fails with NOMEM above it */
 } vbrdf_plan_desc;
 

@@ -22,6 +22,7 @@ E_DEVICE = -4
 E_NUMERIC = -5
 PRECISION_FP64 = 0
 FLAG_STAGE_TIMING = 1
+FLAG_GRAPH = 2
 ABI_VERSION = 1
 MAX_N = 128
 

@@ -113,10 +113,14 @@ struct vbrdf_plan {
   double* quad_d = nullptr;
   double* ws_d = nullptr;
   bool timing = false;
+  bool graph = false;             // capture the solve into a hipGraph and replay it
+  hipGraphExec_t gexec = nullptr;  // instantiated for the pointers in gkey
+  const void* gkey[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int timed = 0;  // solves recorded since the last stage_times query (capped at kTimedSolves)
   std::vector<hipEvent_t> ev;  // kTimedSolves sets of kNumStages + 1 events
 
   ~vbrdf_plan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     if (layers_d) (void)hipFree(layers_d);
@@ -154,7 +158,10 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
   if (d->n_layers < 1) return fail(VBRDF_E_INVALID, "n_layers must be >= 1");
   if (!d->N || !d->L || !d->M || !d->n_dphi) return fail(VBRDF_E_INVALID, "null shape array");
   if (d->precision != VBRDF_PRECISION_FP64) return fail(VBRDF_E_UNSUPPORTED, "unknown precision %d", d->precision);
-  if (d->flags & ~VBRDF_FLAG_STAGE_TIMING) return fail(VBRDF_E_UNSUPPORTED, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(VBRDF_FLAG_STAGE_TIMING | VBRDF_FLAG_GRAPH))
+    return fail(VBRDF_E_UNSUPPORTED, "unknown flags 0x%x", d->flags);
+  if ((d->flags & VBRDF_FLAG_STAGE_TIMING) && (d->flags & VBRDF_FLAG_GRAPH))
+    return fail(VBRDF_E_UNSUPPORTED, "stage timing and graph replay cannot be combined");
   for (int l = 0; l < d->n_layers; ++l) {
     const int N = d->N[l], L = d->L[l], M = d->M[l], P = d->n_dphi[l];
     if (N < 1 || L < 1 || M < 1 || P < 1) return fail(VBRDF_E_INVALID, "layer %d: N, L, M, n_dphi must be >= 1", l);
@@ -222,6 +229,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     delete p;
     return st;
   }
+  p->graph = (d->flags & VBRDF_FLAG_GRAPH) != 0;
   if (d->flags & VBRDF_FLAG_STAGE_TIMING) {
     p->timing = true;
     p->ev.assign((size_t)kTimedSolves * (kNumStages + 1), nullptr);
@@ -260,14 +268,11 @@ size_t vbrdf_plan_output_bytes(const vbrdf_plan* plan) { return plan ? plan->out
 
 size_t vbrdf_plan_workspace_bytes(const vbrdf_plan* plan) { return plan ? plan->ws_bytes : 0; }
 
-vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, const double* coef, double* F_r,
-                         int32_t* layer_status, void* stream) {
-  if (!p) return fail(VBRDF_E_INVALID, "null plan");
-  if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+// The launch sequence of one solve on stream s (events between stages when evs is given).
+static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const double* coef, double* F_r,
+                    int32_t* layer_status, hipStream_t s, bool rec) {
   const int ni = p->n_items, mn = p->max_n, mN = p->max_N;
   int stage = 0;
-  const bool rec = p->timing && p->timed < kTimedSolves;
   hipEvent_t* evs = rec ? &p->ev[(size_t)p->timed * (kNumStages + 1)] : nullptr;
   auto mark = [&]() {
     if (rec) (void)hipEventRecord(evs[stage], s);
@@ -308,6 +313,41 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
   mark();
   k_synth<<<p->n_tasks, 256, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
   mark();
+}
+
+vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, const double* coef, double* F_r,
+                         int32_t* layer_status, void* stream) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (p->graph) {
+    if (!s) return fail(VBRDF_E_INVALID, "graph replay needs a non-default stream");
+    const void* key[6] = {tau, omega, coef, F_r, layer_status, stream};
+    bool same = p->gexec != nullptr;
+    for (int i = 0; i < 6; ++i) same = same && key[i] == p->gkey[i];
+    if (!same) {
+      if (p->gexec) {
+        HIP_TRY(hipGraphExecDestroy(p->gexec));
+        p->gexec = nullptr;
+      }
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      enqueue(p, tau, omega, coef, F_r, layer_status, s, false);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(s, &g);
+      if (ec != hipSuccess) return fail(VBRDF_E_DEVICE, "stream capture: %s", hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        p->gexec = nullptr;
+        return fail(VBRDF_E_DEVICE, "graph instantiation: %s", hipGetErrorString(ei));
+      }
+      for (int i = 0; i < 6; ++i) p->gkey[i] = key[i];
+    }
+    HIP_TRY(hipGraphLaunch(p->gexec, s));
+    return VBRDF_OK;
+  }
+  const bool rec = p->timing && p->timed < kTimedSolves;
+  enqueue(p, tau, omega, coef, F_r, layer_status, s, rec);
   if (rec) ++p->timed;
   HIP_TRY(hipGetLastError());
   return VBRDF_OK;

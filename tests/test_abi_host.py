@@ -58,6 +58,7 @@ def test_gauss_nodes_rejects_bad_order():
     (dict(N=[8], L=[600], M=[600], n_dphi=[8]), binding.E_UNSUPPORTED),  # M above the maximum
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], precision=7), binding.E_UNSUPPORTED),
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=4), binding.E_UNSUPPORTED),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=3), binding.E_UNSUPPORTED),  # timing + graph
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace_cap_bytes=1024), binding.E_NOMEM),
 ])
 def test_plan_validation(kw, code):

@@ -186,3 +186,37 @@ def test_stage_timing():
     assert list(times) == ["validate", "legendre", "assemble", "gemm_FE", "eigen", "gemm_U", "hqapply", "gemm_V",
                            "vfix", "colscal", "bcbuild", "lu", "trsm", "response", "synth"]
     assert all(v >= 0 for v in times.values())
+
+
+def test_graph_replay_matches_eager():
+    """FLAG_GRAPH: the captured sequence, replayed several times with eager work and
+    synchronisations in between and re-captured for new output pointers, gives the eager result
+    bit for bit."""
+    l = dict(N=10, coef=hg(13, 12), M=12, P=8, tau=2.0, omega=0.95)
+    dev = "cuda"
+    c = torch.as_tensor(pack_coefficients([l["coef"]]), device=dev)
+    t = torch.tensor([l["tau"]], dtype=torch.float64, device=dev)
+    w = torch.tensor([l["omega"]], dtype=torch.float64, device=dev)
+    eager = binding.Plan([10], [12], [12], [8])
+    Fe = torch.empty(eager.output_bytes() // 8, dtype=torch.float64, device=dev)
+    se = torch.empty(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        eager.solve(t, w, c, Fe, se, stream.cuda_stream)
+    stream.synchronize()
+    graph = binding.Plan([10], [12], [12], [8], flags=binding.FLAG_GRAPH)
+    outs = [torch.full_like(Fe, float("nan")) for _ in range(2)]
+    sg = torch.empty(1, dtype=torch.int32, device=dev)
+    for rep in range(4):
+        F = outs[rep // 2]  # second pair of replays forces a new capture
+        F.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            graph.solve(t, w, c, F, sg, stream.cuda_stream)
+        stream.synchronize()
+        junk = torch.randn(1000, device=dev) @ torch.randn(1000, device=dev)  # eager work in between
+        torch.cuda.synchronize()
+        assert sg.item() == 0
+        assert torch.equal(F, Fe), rep
+    assert np.abs(Fe.cpu().numpy().reshape(10, 10, 8, 4, 4) - oracle_F(l)).max() < TOL * np.abs(oracle_F(l)[..., 0, 0]).max()
+    assert float(junk) == float(junk)
