@@ -294,7 +294,8 @@ static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufG, layer_status);  // U' = Z X
   mark();
-  k_hqapply<<<dim3((mn + 15) / 16, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);  // U = Q U'
+  const int hqt = (mn + 15) / 16;
+  k_hqapply<<<xcd_grid(ni, hqt), 256, 0, s>>>(p->items_d, ni, hqt, p->ws_d, layer_status);  // U = Q U'
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, layer_status);  // V = E~ U
   mark();
@@ -307,7 +308,8 @@ static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const
   mark();
   k_lu<<<dim3(ni, 2), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_trsm<<<dim3(p->trsm_tiles, 2, ni), 64, p->trsm_lds, s>>>(p->items_d, p->ws_d, layer_status);
+  k_trsm<<<xcd_grid(2 * ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d,
+                                                                 layer_status);
   mark();
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
   mark();

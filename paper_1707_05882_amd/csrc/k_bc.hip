@@ -236,22 +236,25 @@ __global__ __launch_bounds__(256) void k_lu(const Item* items, double* ws, int32
   }
 }
 
-// Right division Y = U A^-1 with the factors of k_lu, for S' and T' (blockIdx.y) and a tile of
-// 16 rows of U (blockIdx.x). One wave: four lanes share a row (lane = 4 row + part), each taking
+// Right division Y = U A^-1 with the factors of k_lu, for S' and T' and a tile of 16 rows of U
+// (workgroups ordered so that the tiles of one matrix run on one XCD and share its L2). One wave: four lanes share a row (lane = 4 row + part), each taking
 // every fourth term of the row's dot products, combined by two lane exchanges. The tile is kept
 // in LDS as Bt[c][r] (row stride 17). No workgroup barrier. With W = Y P:
 //   Z Uu = U :  Z_j = (U_j - sum_{c<j} Z_c Uu_cj) / Uu_jj      (j ascending)
 //   W L = Z  :  W_j = Z_j - sum_{c>j} W_c L_cj                 (j descending, unit L)
 // and Y[:, perm[j]] = W[:, j]. The factor column used at step j is the same for all rows: the
 // wave stages it in LDS while the loads of the next column are in flight.
-__global__ __launch_bounds__(64) void k_trsm(const Item* items, double* ws, int32_t* status) {
-  const Item it = items[blockIdx.z];
+__global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status) {
+  int g, tile;
+  xcd_split(blockIdx.x, tiles, g, tile);  // g = 2 item + side; the tiles of one matrix share an XCD
+  if (g >= 2 * n_items) return;
+  const Item it = items[g >> 1];
   if (status[it.layer] != 0) return;
   const int n = it.n, lane = threadIdx.x;
   constexpr int R = kTrsmRows;
-  const int r0 = blockIdx.x * R;
+  const int r0 = tile * R;
   if (r0 >= n) return;
-  const int which = blockIdx.y;
+  const int which = g & 1;
   double* base = ws + it.ws;
   const double* __restrict__ AT = base + (int64_t)(which == 0 ? kBufG : kBufF) * n * n;
   const double* __restrict__ U = base + (int64_t)kBufU * n * n;

@@ -1226,13 +1226,13 @@ __global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, doub
 // U = Q U' for the reflectors of the Hessenberg reduction, Q = H_0 H_1 ... H_{n-3} with
 // H_k = I - tau_k v_k v_k^T on rows k+1..n-1 (v_k and tau_k left in the workspace by k_eigen):
 // U' = Z X from the QR phase becomes the eigenvector matrix of G. One workgroup of 256 threads
-// (16 row groups x 16 columns) per 16 columns; the column block stays in LDS while the reflectors
+// (16 row groups x 16 columns) per 16 columns, the column blocks of one item on one XCD; the column block stays in LDS while the reflectors
 // are applied from the last to the first, each thread's entries of the next reflector (kPer of
 // them, rows i = group + 16 q) loaded while the current one is applied.
 template <int kPer>
-__device__ __forceinline__ void hqapply_body(const Item& it, double* ws, double* sb, double (*red)[16]) {
+__device__ __forceinline__ void hqapply_body(const Item& it, int tile, double* ws, double* sb, double (*red)[16]) {
   const int n = it.n;
-  const int c0 = blockIdx.x * 16;
+  const int c0 = tile * 16;
   if (c0 >= n) return;
   double* base = ws + it.ws;
   const double* __restrict__ QV = base + (int64_t)kBufYS * n * n;
@@ -1292,17 +1292,21 @@ __device__ __forceinline__ void hqapply_body(const Item& it, double* ws, double*
     for (int r = grp; r < n; r += ngrp) U[(int64_t)r * n + c0 + col] = sb[r * 17 + col];
 }
 
-__global__ __launch_bounds__(256) void k_hqapply(const Item* items, double* ws, const int32_t* status) {
-  const Item it = items[blockIdx.y];
+__global__ __launch_bounds__(256) void k_hqapply(const Item* items, int n_items, int tiles, double* ws,
+                                                  const int32_t* status) {
+  int g, tile;
+  xcd_split(blockIdx.x, tiles, g, tile);  // the column blocks of one item share an XCD
+  if (g >= n_items) return;
+  const Item it = items[g];
   if (status[it.layer] != 0) return;
   __shared__ double sb[kMaxn * 17];  // rows x 16 columns, row stride 17
   __shared__ double red[4][16];
   if (it.n <= 128)
-    hqapply_body<8>(it, ws, sb, red);
+    hqapply_body<8>(it, tile, ws, sb, red);
   else if (it.n <= 256)
-    hqapply_body<16>(it, ws, sb, red);
+    hqapply_body<16>(it, tile, ws, sb, red);
   else
-    hqapply_body<32>(it, ws, sb, red);
+    hqapply_body<32>(it, tile, ws, sb, red);
 }
 
 }  // namespace vbrdf

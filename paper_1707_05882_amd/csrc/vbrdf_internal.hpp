@@ -74,12 +74,24 @@ __global__ void k_eigen(const Item* items, double* ws, int32_t* status);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
-__global__ void k_hqapply(const Item* items, double* ws, const int32_t* status);
+__global__ void k_hqapply(const Item* items, int n_items, int tiles, double* ws, const int32_t* status);
 __global__ void k_lu(const Item* items, double* ws, int32_t* status);
-__global__ void k_trsm(const Item* items, double* ws, int32_t* status);
+__global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status);
 // right-hand-side rows per right-division tile (one wave, four lanes per row; the tile takes
 // n x (kTrsmRows + 3) doubles of LDS)
 constexpr int kTrsmRows = 16;
+
+// XCD-aware launch order: workgroups are dealt round-robin to the 8 XCDs (each with its own L2),
+// so the `tiles` workgroups that read one matrix get linear ids that agree mod 8. For `groups`
+// matrices the grid has xcd_grid(groups, tiles) workgroups; xcd_split recovers (group, tile) of a
+// workgroup, group >= groups meaning an idle one.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_grid(int groups, int tiles) { return (groups + kXcds - 1) / kXcds * kXcds * tiles; }
+__host__ __device__ inline void xcd_split(int id, int tiles, int& group, int& tile) {
+  const int blk = id / (kXcds * tiles), rem = id % (kXcds * tiles);
+  tile = rem / kXcds;
+  group = blk * kXcds + rem % kXcds;
+}
 __global__ void k_response(const Item* items, const Layer* layers, const double* quad, double* ws,
                            const int32_t* status);
 __global__ void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
