@@ -220,3 +220,43 @@ def test_graph_replay_matches_eager():
         assert torch.equal(F, Fe), rep
     assert np.abs(Fe.cpu().numpy().reshape(10, 10, 8, 4, 4) - oracle_F(l)).max() < TOL * np.abs(oracle_F(l)[..., 0, 0]).max()
     assert float(junk) == float(junk)
+
+
+def test_large_workload_sampled_outputs():
+    """The large workload (N = 128, 8N = 1024 per order, L = M = n_dphi = 256) at full size in the
+    bench's launch configuration, checked on a sample of F_r (every 16th i and q, every 32nd
+    azimuth) against oracle values stored by tests/golden/make_large_sample.py."""
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "large_sample.npz")
+    g = np.load(path)
+    si, sq, sk = (int(v) for v in g["strides"])
+    w = workload("large")
+    s = BRDFSolver(w.N, w.L, w.M, w.n_dphi)
+    t, om, c = s.upload(w.tau, w.omega, w.coef)
+    s.solve_device(t, om, c)
+    torch.cuda.synchronize()
+    assert s.status.cpu().tolist() == [0]
+    F = s.layer(0)[::si, ::sq, ::sk].cpu().numpy()
+    assert np.isfinite(F).all()
+    assert np.abs(F - g["F"]).max() / float(g["scale"]) < TOL
+
+
+def test_batched_workload_sampled_outputs():
+    """The batched workload (256 layers of uneven N in {16, 24, 32, 48, 64}, L = M = n_dphi = 2N)
+    in one plan, as the bench would run it; every layer must succeed, and three layers (N = 48,
+    64, 16) are checked on a sample of F_r against oracle values stored by
+    tests/golden/make_batched_sample.py."""
+    import os
+
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "batched_sample.npz"))
+    st_ = int(g["stride"])
+    w = workload("batched")
+    s = BRDFSolver(w.N, w.L, w.M, w.n_dphi)
+    t, om, c = s.upload(w.tau, w.omega, w.coef)
+    s.solve_device(t, om, c)
+    torch.cuda.synchronize()
+    assert (s.status.cpu().numpy() == 0).all()
+    for i in (int(v) for v in g["layers"]):
+        F = s.layer(i)[::st_, ::st_, ::st_].cpu().numpy()
+        assert np.abs(F - g[f"F{i}"]).max() / float(g[f"scale{i}"]) < TOL, i
