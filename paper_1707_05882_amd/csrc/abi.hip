@@ -306,7 +306,7 @@ static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const
   const int et = (mn + 15) / 16;
   k_bcbuild<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_lu<<<dim3(ni, 2), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
   k_trsm<<<xcd_grid(2 * ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d,
                                                                  layer_status);

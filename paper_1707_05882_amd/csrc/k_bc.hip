@@ -195,7 +195,7 @@ __device__ inline int* lu_perm(double* ex, int n, int which) {
 // LU factorisation with partial pivoting of S' (blockIdx.y = 0) or T' (1), P^T A = L Uu. The
 // factor is written transposed, AT[j n + c] = A(c, j), so that column j of Uu (c < j) and of L
 // (c > j) are contiguous for the right division; pivots and 1 / Uu_kk go to the extras block.
-__global__ __launch_bounds__(256) void k_lu(const Item* items, double* ws, int32_t* status) {
+__global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int32_t* status) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
   const int n = it.n, tid = threadIdx.x, NT = blockDim.x;
