@@ -1001,48 +1001,56 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       }
       if (sb > 0) fetch_rows((blk[sb - 1] == 0) ? sb - 2 : sb - 1, sb - 1);
       __syncthreads();
-      for (int j = tid; j < n; j += NT) {
-        const double wr = lre[j], wi = lim[j];
-        if (wi < 0.0) continue;
-        const int b0 = (blk[j] == 0) ? j - 1 : j;
-        if (i >= b0) continue;  // this block is not above the eigenvector's own block
-        const int bend = (blk[b0] == 2) ? b0 + 1 : b0;
-        const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
+      // four lanes per eigenvector: each sums every fourth term of the row products, combined by
+      // two lane exchanges (outside any per-eigenvector branch), then lane 0 of the four solves
+      const int lpv = (NT >= 64) ? 4 : 1;  // lanes per eigenvector (1 only for tiny test blocks)
+      for (int j0 = 0; j0 < n; j0 += NT / lpv) {
+        const int j = j0 + tid / lpv, part = tid % lpv;
+        bool act = j < n;
+        double wr = 0.0, wi = 0.0;
+        int b0 = 0, bend = 0;
+        if (act) {
+          wr = lre[j];
+          wi = lim[j];
+          b0 = (blk[j] == 0) ? j - 1 : j;
+          bend = (blk[b0] == 2) ? b0 + 1 : b0;
+          act = !(wi < 0.0) && i < b0;  // second member of a pair, or not above the own block
+        }
         const bool cplx = wi > 0.0;
-        const Cx lam{wr, wi};
         const double* ts = trow;
         const double* ti = trow + n;
-        Cx r0{0.0, 0.0}, r1{0.0, 0.0};
-        if (cplx) {
-          for (int c = i + 1; c <= bend; ++c) {
-            const double xr = X[c * ld + j], xi = X[c * ld + j + 1];
-            r0.re -= ts[c] * xr;
-            r0.im -= ts[c] * xi;
-            if (sb < i) {
-              r1.re -= ti[c] * xr;
-              r1.im -= ti[c] * xi;
+        double p0r = 0.0, p0i = 0.0, p1r = 0.0, p1i = 0.0;
+        if (act) {
+          if (cplx) {
+            for (int c = i + 1 + part; c <= bend; c += lpv) {
+              const double xr = X[c * ld + j], xi = X[c * ld + j + 1];
+              p0r -= ts[c] * xr;
+              p0i -= ts[c] * xi;
+              p1r -= ti[c] * xr;
+              p1i -= ti[c] * xi;
+            }
+          } else {
+            for (int c = i + 1 + part; c <= bend; c += lpv) {
+              const double xc = X[c * ld + j];
+              p0r -= ts[c] * xc;
+              p1r -= ti[c] * xc;
             }
           }
-        } else if (sb == i) {
-          double a0 = 0.0, a1 = 0.0;
-          int c = i + 1;
-          for (; c + 1 <= bend; c += 2) {
-            a0 -= ts[c] * X[c * ld + j];
-            a1 -= ts[c + 1] * X[(c + 1) * ld + j];
-          }
-          if (c <= bend) a0 -= ts[c] * X[c * ld + j];
-          r0.re = a0 + a1;
-        } else {
-          double a0 = 0.0, a1 = 0.0;
-#pragma unroll 4
-          for (int c = i + 1; c <= bend; ++c) {
-            const double xc = X[c * ld + j];
-            a0 -= ts[c] * xc;
-            a1 -= ti[c] * xc;
-          }
-          r0.re = a0;
-          r1.re = a1;
         }
+        if (lpv == 4) {
+          p0r += __shfl_xor(p0r, 1);
+          p0i += __shfl_xor(p0i, 1);
+          p1r += __shfl_xor(p1r, 1);
+          p1i += __shfl_xor(p1i, 1);
+          p0r += __shfl_xor(p0r, 2);
+          p0i += __shfl_xor(p0i, 2);
+          p1r += __shfl_xor(p1r, 2);
+          p1i += __shfl_xor(p1i, 2);
+        }
+        if (!act || part != 0) continue;
+        const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
+        const Cx lam{wr, wi};
+        const Cx r0{p0r, p0i}, r1{p1r, p1i};
         if (sb == i) {
           const Cx d0 = csub(Cx{ti[i], 0.0}, lam);
           const Cx xi = (cabs1(d0) <= same) ? Cx{0.0, 0.0} : cdiv(r0, cguard(d0, smin));
