@@ -236,10 +236,11 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
   }
 }
 
-// Right division Y = U A^-1 with the factors of k_lu, for S' and T' and a tile of 16 rows of U
-// (workgroups ordered so that the tiles of one matrix run on one XCD and share its L2). One wave: four lanes share a row (lane = 4 row + part), each taking
-// every fourth term of the row's dot products, combined by two lane exchanges. The tile is kept
-// in LDS as Bt[c][r] (row stride 17). No workgroup barrier. With W = Y P:
+// Right division Y = U A^-1 with the factors of k_lu, for S' and T' and a tile of kTrsmRows rows of
+// U (workgroups ordered so that the tiles of one matrix run on one XCD and share its L2). One wave:
+// kLpr = 64 / kTrsmRows lanes share a row (lane = kLpr row + part), each taking every kLpr-th term
+// of the row's dot products, combined by lane exchanges. The tile is kept in LDS as Bt[c][r] (row
+// stride kTrsmRows + 1). No workgroup barrier. With W = Y P:
 //   Z Uu = U :  Z_j = (U_j - sum_{c<j} Z_c Uu_cj) / Uu_jj      (j ascending)
 //   W L = Z  :  W_j = Z_j - sum_{c>j} W_c L_cj                 (j descending, unit L)
 // and Y[:, perm[j]] = W[:, j]. The factor column used at step j is the same for all rows: the
@@ -291,7 +292,8 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   };
-  const int row = lane >> 2, part = lane & 3;
+  constexpr int kLpr = 64 / R;  // lanes per right-hand-side row
+  const int row = lane / kLpr, part = lane % kLpr;
   double* b = Bt + row;
   const bool own = row < nr;
   // Z Uu = U, j ascending
@@ -303,14 +305,13 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
     if (j + 1 < n) fetch(j + 1);
     double a0 = 0.0, a1 = 0.0;
     int c = part;
-    for (; c + 4 < j; c += 8) {
+    for (; c + kLpr < j; c += 2 * kLpr) {
       a0 -= b[c * ldb] * col[c];
-      a1 -= b[(c + 4) * ldb] * col[c + 4];
+      a1 -= b[(c + kLpr) * ldb] * col[c + kLpr];
     }
     if (c < j) a0 -= b[c * ldb] * col[c];
     double acc = a0 + a1;
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
+    for (int o = 1; o < kLpr; o <<= 1) acc += __shfl_xor(acc, o);
     if (own && part == 0) b[j * ldb] = (b[j * ldb] + acc) * id[j];
     sync();  // the new entry and every read of the buffer the next stash overwrites are done
     if (j + 1 < n) stash(cb + ((j + 1) & 1) * n);
@@ -325,14 +326,13 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
     if (j > 0) fetch(j - 1);
     double a0 = 0.0, a1 = 0.0;
     int c = j + 1 + part;
-    for (; c + 4 < n; c += 8) {
+    for (; c + kLpr < n; c += 2 * kLpr) {
       a0 -= b[c * ldb] * col[c];
-      a1 -= b[(c + 4) * ldb] * col[c + 4];
+      a1 -= b[(c + kLpr) * ldb] * col[c + kLpr];
     }
     if (c < n) a0 -= b[c * ldb] * col[c];
     double acc = a0 + a1;
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
+    for (int o = 1; o < kLpr; o <<= 1) acc += __shfl_xor(acc, o);
     if (own && part == 0) b[j * ldb] += acc;
     sync();
     if (j > 0) stash(cb + ((j - 1) & 1) * n);

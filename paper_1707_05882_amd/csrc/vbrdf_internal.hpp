@@ -77,9 +77,9 @@ __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
 __global__ void k_hqapply(const Item* items, int n_items, int tiles, double* ws, const int32_t* status);
 __global__ void k_lu(const Item* items, double* ws, int32_t* status);
 __global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status);
-// right-hand-side rows per right-division tile (one wave, four lanes per row; the tile takes
+// right-hand-side rows per right-division tile (one wave, 64 / kTrsmRows lanes per row; the tile takes
 // n x (kTrsmRows + 3) doubles of LDS)
-constexpr int kTrsmRows = 16;
+constexpr int kTrsmRows = 8;
 
 // XCD-aware launch order: workgroups are dealt round-robin to the 8 XCDs (each with its own L2),
 // so the `tiles` workgroups that read one matrix get linear ids that agree mod 8. For `groups`
