@@ -110,73 +110,102 @@ __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status) 
   }
 }
 
-// In-place LU factorisation with partial pivoting, P^T A = L Uu (row perm[k] of the original at
-// position k), unit L below the diagonal, invd[k] = 1 / Uu_kk. A has row stride ld and lives in LDS
-// or global memory (the caller passes a pointer derived from the __shared__ array so the accesses
-// compile to LDS instructions). Returns false (uniformly) on a zero or non-finite pivot.
-// Per column, wave 0 alone finds the pivot (largest modulus, ties to the smaller row), swaps the
-// rows and scales the column, lane-synchronous; then all waves apply the rank-1 update: two
-// workgroup barriers per column. The block size is a multiple of 64 (or below 64).
-__device__ __forceinline__ bool lu_factor(double* A, int64_t ld, int n, int* perm, double* invd, double* redv,
-                                          int* redi) {
-  const int tid = threadIdx.x, NT = blockDim.x;
-  const int W = NT < 64 ? NT : 64, lane = tid % W, wv = tid / W, nw = NT / W;
-  auto wsync = [] {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  };
-  for (int i = tid; i < n; i += NT) perm[i] = i;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (wv == 0) {
-      double best = -1.0;
-      int bi = n;
-      for (int i = k + lane; i < n; i += W) {
-        const double v = fabs(A[(int64_t)i * ld + k]);
-        if (v > best || (v == best && i < bi)) {
-          best = v;
+// LU factorisation with partial pivoting, P^T A = L Uu, in place and with the row exchanges kept
+// logical: A keeps its original row order, perm[k] is the original row that holds position k of
+// the factor, and so L(k', k) = A(perm[k'], k) for k' > k (unit diagonal), Uu(k, c) =
+// A(perm[k], c) for c >= k, invd[k] = 1 / Uu_kk. A has row stride ld and lives in LDS or global
+// memory (the caller passes a pointer derived from the __shared__ array so the accesses compile to
+// LDS instructions). perm holds 2n ints (two position buffers); on return perm[0, n) is the final
+// order. Returns false (uniformly) on a zero or non-finite pivot.
+// Look-ahead by one column: while waves 1.. apply the rank-1 update of step k to columns k+2..,
+// wave 0 updates column k+1 by step k, picks its pivot (largest modulus, ties to the smaller
+// position) and scales it, lane-synchronous and in registers. One workgroup barrier per column.
+// The block is a multiple of 64 threads and n <= 64 kPer.
+template <int kPer>
+__device__ __forceinline__ bool lu_factor(double* A, int64_t ld, int n, int* perm, double* invd, int* redi) {
+  const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
+  const bool upd = nw == 1 || wv > 0;  // waves taking the rank-1 updates
+  const int uw = nw == 1 ? 0 : wv - 1, unw = nw == 1 ? 1 : nw - 1;
+  // Column j at positions j..n-1 (src), after the update of step j-1 for j > 0; the new order goes
+  // to dst.
+  auto panel = [&](int j, const int* src, int* dst) {
+    double u = 0.0;
+    if (j > 0) u = A[(int64_t)src[j - 1] * ld + j];  // Uu(j-1, j)
+    double v[kPer];
+    int ph[kPer];
+    double best = -1.0, bval = 0.0;
+    int bi = n;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = j + lane + 64 * q;
+      if (i < n) {
+        ph[q] = src[i];
+        double x = A[(int64_t)ph[q] * ld + j];
+        if (j > 0) x -= A[(int64_t)ph[q] * ld + j - 1] * u;
+        v[q] = x;
+        if (fabs(x) > best) {  // positions ascend within a lane: ties keep the first
+          best = fabs(x);
+          bval = x;
           bi = i;
         }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        if (o < W) {
-          const double ov = __shfl_xor(best, o);
-          const int oi = __shfl_xor(bi, o);
-          if (ov > best || (ov == best && oi < bi)) {
-            best = ov;
-            bi = oi;
-          }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o), ov = __shfl_xor(bval, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bval = ov;
+        bi = oi;
+      }
+    }
+    const bool ok = best > 0.0 && isfinite(best);
+    if (ok) {
+      const double inv = 1.0 / bval;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int i = j + lane + 64 * q;
+        if (i < n) A[(int64_t)ph[q] * ld + j] = (i == bi) ? v[q] : v[q] * inv;
+      }
+      const int pj = src[j], pb = src[bi];
+      for (int i = lane; i < n; i += 64) dst[i] = (i == j) ? pb : (i == bi ? pj : src[i]);
+      if (lane == 0) invd[j] = inv;
+    }
+    if (lane == 0) redi[j & 1] = ok ? 1 : 0;
+  };
+  for (int i = tid; i < n; i += NT) perm[n + i] = i;
+  __syncthreads();
+  if (wv == 0) panel(0, perm + n, perm);
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (!redi[k & 1]) return false;
+    if (k + 1 == n) break;
+    const int* cur = perm + (k & 1) * n;
+    if (wv == 0) panel(k + 1, cur, perm + ((k + 1) & 1) * n);
+    if (upd) {
+      // rank-1 update of step k on columns k+2..: lane l takes columns k+2+l, k+2+l+64, ..., and
+      // the updating waves share the positions k+1.. (row multiplier read once per row)
+      const int pk = cur[k];
+      double akc[kPer];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int c = k + 2 + lane + 64 * q;
+        akc[q] = c < n ? A[(int64_t)pk * ld + c] : 0.0;
+      }
+      for (int i = k + 1 + uw; i < n; i += unw) {
+        const int r = cur[i];
+        const double l = A[(int64_t)r * ld + k];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+          const int c = k + 2 + lane + 64 * q;
+          if (c < n) A[(int64_t)r * ld + c] -= l * akc[q];
         }
       }
-      const bool ok = best > 0.0 && isfinite(best);
-      if (ok && bi != k) {
-        for (int c = lane; c < n; c += W) {
-          const double t = A[(int64_t)k * ld + c];
-          A[(int64_t)k * ld + c] = A[(int64_t)bi * ld + c];
-          A[(int64_t)bi * ld + c] = t;
-        }
-      }
-      wsync();
-      if (ok) {
-        const double inv = 1.0 / A[(int64_t)k * ld + k];
-        for (int i = k + 1 + lane; i < n; i += W) A[(int64_t)i * ld + k] *= inv;
-        if (lane == 0) {
-          invd[k] = inv;
-          const int t = perm[k];
-          perm[k] = perm[bi];
-          perm[bi] = t;
-        }
-      }
-      if (lane == 0) redi[k & 1] = ok ? 1 : 0;
     }
     __syncthreads();
-    if (!redi[k & 1]) return false;
-    // trailing update: lane l of wave w takes columns k+1+l, k+1+l+64, ... and rows k+1+w,
-    // k+1+w+nw, ... (no index division; A(i, k) is the same address for a whole wave)
-    for (int c = k + 1 + lane; c < n; c += W) {
-      const double akc = A[(int64_t)k * ld + c];
-      for (int i = k + 1 + wv; i < n; i += nw) A[(int64_t)i * ld + c] -= A[(int64_t)i * ld + k] * akc;
-    }
+  }
+  if ((n - 1) & 1) {  // the final order is in the second buffer
+    for (int i = tid; i < n; i += NT) perm[i] = perm[n + i];
     __syncthreads();
   }
   return true;
@@ -205,9 +234,8 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
   double* AT = base + (int64_t)(which == 0 ? kBufG : kBufF) * n * n;
   double* ex = base + extras_off(n);
   __shared__ double smem[kLuLds];
-  __shared__ int perm[kMaxn];
+  __shared__ int perm[2 * kMaxn];
   __shared__ double invd[kMaxn];
-  __shared__ double redv[8];
   __shared__ int redi[8];
   const bool in_lds = n <= kLdsMaxn;
   double* A = in_lds ? smem : Ag;
@@ -216,9 +244,9 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
   if (in_lds) {
     for (int t = tid; t < n * n; t += NT) smem[(t / n) * (n + 1) + (t % n)] = Ag[t];
     __syncthreads();
-    ok = lu_factor(smem, n + 1, n, perm, invd, redv, redi);
+    ok = lu_factor<kLdsMaxn / 64>(smem, n + 1, n, perm, invd, redi);
   } else {
-    ok = lu_factor(Ag, n, n, perm, invd, redv, redi);
+    ok = lu_factor<kMaxn / 64>(Ag, n, n, perm, invd, redi);
   }
   if (!ok) {
     if (tid == 0) status[it.layer] = -5;
@@ -226,7 +254,7 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
   }
   for (int t = tid; t < n * n; t += NT) {
     const int j = t / n, c = t % n;
-    AT[t] = A[(int64_t)c * ld + j];
+    AT[t] = A[(int64_t)perm[c] * ld + j];
   }
   double* id = lu_invd(ex, n, which);
   int* pm = lu_perm(ex, n, which);
@@ -418,7 +446,7 @@ __device__ __forceinline__ void vfix_body(const Item& it, double* base, int32_t*
     for (int t = tid; t < n * n; t += NT) A[(int64_t)(t / n) * ld + (t % n)] = Fg[t];
     __syncthreads();
   }
-  if (!lu_factor(A, ld, n, perm, invd, redv, redi)) {
+  if (!lu_factor<(kLds ? kLdsMaxn : kMaxn) / 64>(A, ld, n, perm, invd, redi)) {
     if (tid == 0) status[it.layer] = -5;
     return;
   }
@@ -435,14 +463,14 @@ __device__ __forceinline__ void vfix_body(const Item& it, double* base, int32_t*
       __syncthreads();
       for (int k = 0; k + 1 < n; ++k) {  // L y = P^T u
         const double xk = x[k];
-        for (int r = k + 1 + tid; r < n; r += NT) x[r] -= A[(int64_t)r * ld + k] * xk;
+        for (int r = k + 1 + tid; r < n; r += NT) x[r] -= A[(int64_t)perm[r] * ld + k] * xk;
         __syncthreads();
       }
       for (int k = n - 1; k >= 0; --k) {  // Uu z = y
         if (tid == 0) x[k] *= invd[k];
         __syncthreads();
         const double xk = x[k];
-        for (int r = tid; r < k; r += NT) x[r] -= A[(int64_t)r * ld + k] * xk;
+        for (int r = tid; r < k; r += NT) x[r] -= A[(int64_t)perm[r] * ld + k] * xk;
         __syncthreads();
       }
     }
@@ -464,7 +492,7 @@ __global__ __launch_bounds__(256) void k_vfix(const Item* items, double* ws, int
   if (status[it.layer] != 0) return;
   double* base = ws + it.ws;
   __shared__ double smem[kVfixLds];
-  __shared__ int perm[kMaxn];
+  __shared__ int perm[2 * kMaxn];
   __shared__ double invd[kMaxn];
   __shared__ double redv[8];
   __shared__ int redi[8];
