@@ -103,6 +103,7 @@ __global__ void k_legendre(const Item* items, const Layer* layers, const double*
 
 constexpr int kAsmTile = 16;   // 16 x 16 node pairs (4x4 Stokes blocks) per workgroup
 constexpr int kAsmChunk = 32;  // degrees staged per LDS pass
+static_assert(kAsmChunk % 2 == 0, "degree parity within a chunk follows the degree index");
 
 // One workgroup per (item, tile of output node i, tile of input node j); one thread per (i, j)
 // Stokes block. Legendre values and coefficients of a chunk of degrees are staged in LDS and
@@ -148,33 +149,40 @@ __global__ __launch_bounds__(256) void k_assemble(const Item* items, const Layer
       sC[row][l] = cf[(int64_t)row * L + lc + l];
     }
     __syncthreads();
-    for (int l = 0; l < cnt; ++l) {
-      const int e = (lc + l - m) & 1;
+    // Degree l of the chunk has parity (lc + l - m) & 1 = l & 1 (chunks start at even offsets
+    // from m), so pairs of degrees keep every accumulator index constant (registers, no scratch).
+    auto acc = [&](double* Q, double* U, int l) __attribute__((always_inline)) {
       const double pi_ = sPi[l][ti][0], ri = sPi[l][ti][1], tI = sPi[l][ti][2];
       const double pj = sPj[l][tj][0], rj = sPj[l][tj][1], tJ = sPj[l][tj][2];
       const double a1 = sC[0][l], a2 = sC[1][l], a3 = sC[2][l], a4 = sC[3][l];
       const double b1 = sC[4][l], b2 = sC[5][l];
       // IQ part: Pi B_l diag(1,1,0,0) Pj
-      q[e][0] += pi_ * a1 * pj;
-      q[e][1] += pi_ * b1 * rj;
-      q[e][2] += pi_ * b1 * tJ;
-      q[e][3] += ri * b1 * pj;
-      q[e][4] += ri * a2 * rj;
-      q[e][5] += ri * a2 * tJ;
-      q[e][6] += tI * b1 * pj;
-      q[e][7] += tI * a2 * rj;
-      q[e][8] += tI * a2 * tJ;
+      Q[0] += pi_ * a1 * pj;
+      Q[1] += pi_ * b1 * rj;
+      Q[2] += pi_ * b1 * tJ;
+      Q[3] += ri * b1 * pj;
+      Q[4] += ri * a2 * rj;
+      Q[5] += ri * a2 * tJ;
+      Q[6] += tI * b1 * pj;
+      Q[7] += tI * a2 * rj;
+      Q[8] += tI * a2 * tJ;
       // UV part: Pi B_l diag(0,0,1,1) Pj
-      u[e][0] += tI * a3 * tJ;
-      u[e][1] += tI * a3 * rj;
-      u[e][2] += tI * b2 * pj;
-      u[e][3] += ri * a3 * tJ;
-      u[e][4] += ri * a3 * rj;
-      u[e][5] += ri * b2 * pj;
-      u[e][6] += pi_ * b2 * tJ;
-      u[e][7] += pi_ * b2 * rj;
-      u[e][8] += pi_ * a4 * pj;
+      U[0] += tI * a3 * tJ;
+      U[1] += tI * a3 * rj;
+      U[2] += tI * b2 * pj;
+      U[3] += ri * a3 * tJ;
+      U[4] += ri * a3 * rj;
+      U[5] += ri * b2 * pj;
+      U[6] += pi_ * b2 * tJ;
+      U[7] += pi_ * b2 * rj;
+      U[8] += pi_ * a4 * pj;
+    };
+    int l = 0;
+    for (; l + 1 < cnt; l += 2) {
+      acc(q[0], u[0], l);
+      acc(q[1], u[1], l + 1);
     }
+    if (l < cnt) acc(q[0], u[0], l);
   }
   if (i >= N || j >= N) return;
 
