@@ -72,9 +72,10 @@ __device__ inline double wseq_value(WSeq& q, int l, double x) {
   return nxt;
 }
 
-// Legendre table per item: leg[(l * N + i) * 3 + {0,1,2}] = (Pb, R, T) of order m at mu_i.
-__global__ void k_legendre(const Item* items, const Layer* layers, const double* quad, double* ws,
-                           const int32_t* status) {
+// Legendre table per item: leg[(l * N + i) * 3 + {0,1,2}] = (Pb, R, T) of order m at mu_i. One
+// thread per node; launched with 128 threads (N <= 128).
+__global__ __launch_bounds__(128) void k_legendre(const Item* items, const Layer* layers, const double* quad,
+                                                  double* ws, const int32_t* status) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
   const Layer ly = layers[it.layer];

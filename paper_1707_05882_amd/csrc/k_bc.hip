@@ -268,7 +268,7 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
 // U (workgroups ordered so that the tiles of one matrix run on one XCD and share its L2). One wave:
 // kLpr = 64 / kTrsmRows lanes share a row (lane = kLpr row + part), each taking every kLpr-th term
 // of the row's dot products, combined by lane exchanges. The tile is kept in LDS as Bt[c][r] (row
-// stride kTrsmRows + 1). No workgroup barrier. With W = Y P:
+// stride kTrsmLdb). No workgroup barrier. With W = Y P:
 //   Z Uu = U :  Z_j = (U_j - sum_{c<j} Z_c Uu_cj) / Uu_jj      (j ascending)
 //   W L = Z  :  W_j = Z_j - sum_{c>j} W_c L_cj                 (j descending, unit L)
 // and Y[:, perm[j]] = W[:, j]. The factor column used at step j is the same for all rows: the
@@ -291,9 +291,9 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
   double* ex = base + extras_off(n);
   const double* __restrict__ id = lu_invd(ex, n, which);
   const int* __restrict__ pm = lu_perm(ex, n, which);
-  // LDS: Bt [n][R + 1], then two factor-column buffers [2][n]
+  // LDS: Bt [n][kTrsmLdb], then two factor-column buffers [2][n]
   HIP_DYNAMIC_SHARED(double, smem)
-  constexpr int ldb = R + 1;
+  constexpr int ldb = kTrsmLdb;
   double* Bt = smem;
   double* cb = smem + (int64_t)n * ldb;
   const int nr = min(R, n - r0);

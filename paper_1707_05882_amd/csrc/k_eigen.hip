@@ -168,6 +168,19 @@ __device__ __forceinline__ void apply_zop(const ZOp& op, const double* rf, doubl
   }
 }
 
+// Line (row or column) of a thread in the two-sided Hessenberg update, where P adjacent lanes
+// share a line and split its dot product (part = tid mod P, element i of the line taken by part
+// i mod P). In LDS, element (r, c) sits in bank pair (r + c) mod 16 of the 32 banks (row stride
+// 1 mod 16 doubles), and a 64-bit access is served 16 lanes at a time, so lines handled together
+// must be P apart: half-wave h covers lines 32 (h / P) + P j + h mod P, j < 32 / P, and every 16
+// lanes of it meet 16 distinct bank pairs. Blocks too small for that keep consecutive lines.
+// Either way tid -> line is a bijection onto [0, NT / P).
+__device__ inline int hess_line(int tid, int P, int NT) {
+  if (NT % (32 * P) != 0) return tid / P;
+  const int hw = tid >> 5, l32 = tid & 31;
+  return 32 * (hw / P) + P * (l32 / P) + hw % P;
+}
+
 template <bool kLds>
 __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t* status, double* sH, double* srefl,
                                            double* sred, int* sctl, double* sxyz, ZOp* zops) {
@@ -221,6 +234,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
   double* __restrict__ QV = base + (int64_t)kBufYS * n * n;  // v_k at QV[k n + i], tau_k at QV[(n-1) n + k]
   int Pr = 1;
   while (Pr < 4 && n * Pr * 2 <= NT) Pr *= 2;
+  const int line_r = hess_line(tid, Pr, NT);
   for (int k = 0; k + 2 < n; ++k) {
     const int len = n - k - 1;
     double part = 0.0;
@@ -254,8 +268,9 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     int Pl = 1;
     while (Pl < 8 && len * Pl * 2 <= NT) Pl *= 2;
     const int part_l = tid & (Pl - 1);
+    const int line_l = hess_line(tid, Pl, NT);
     for (int c0 = k + 1; c0 < n; c0 += NT / Pl) {
-      const int c = c0 + tid / Pl;
+      const int c = c0 + line_l;
       double w = 0.0;
       if (c < n) {
         if (part_l == 0) w = HH(k + 1, c) * dlt;
@@ -274,7 +289,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     // right: H (I - tau v v^T), rows 0..n-1
     const int part_r = tid & (Pr - 1);
     for (int r0 = 0; r0 < n; r0 += NT / Pr) {
-      const int r = r0 + tid / Pr;
+      const int r = r0 + line_r;
       double y = 0.0;
       if (r < n) {
         if (part_r == 0) y = HH(r, k + 1);
