@@ -294,8 +294,8 @@ static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufG, layer_status);  // U' = Z X
   mark();
-  const int hqt = (mn + 15) / 16;
-  k_hqapply<<<xcd_grid(ni, hqt), 256, 0, s>>>(p->items_d, ni, hqt, p->ws_d, layer_status);  // U = Q U'
+  const int hqt = (mn + kHqCols - 1) / kHqCols;
+  k_hqapply<<<xcd_grid(ni, hqt), 64, 0, s>>>(p->items_d, ni, hqt, p->ws_d, layer_status);  // U = Q U'
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, layer_status);  // V = E~ U
   mark();

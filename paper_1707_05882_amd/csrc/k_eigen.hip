@@ -1248,88 +1248,94 @@ __global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, doub
 
 // U = Q U' for the reflectors of the Hessenberg reduction, Q = H_0 H_1 ... H_{n-3} with
 // H_k = I - tau_k v_k v_k^T on rows k+1..n-1 (v_k and tau_k left in the workspace by k_eigen):
-// U' = Z X from the QR phase becomes the eigenvector matrix of G. One workgroup of 256 threads
-// (16 row groups x 16 columns) per 16 columns, the column blocks of one item on one XCD; the column block stays in LDS while the reflectors
-// are applied from the last to the first, each thread's entries of the next reflector (kPer of
-// them, rows i = group + 16 q) loaded while the current one is applied.
+// U' = Z X from the QR phase becomes the eigenvector matrix of G. One wave per kHqCols columns,
+// the column blocks of one item on one XCD. The block stays in LDS (row stride kHqCols) while the
+// reflectors are applied from the last to the first. Lane = kHqCols part + column: the 16 parts
+// of a column split the dot product v^T u (rows i = part + 16 q, kPer of them per lane) and
+// combine it by lane exchanges, so no workgroup barrier is needed; each lane's entries of a
+// reflector are loaded a few steps before it is applied. 16 consecutive lanes touch 16
+// consecutive doubles (no LDS bank conflict).
+static_assert(64 % kHqCols == 0, "a wave holds whole columns");
 template <int kPer>
-__device__ __forceinline__ void hqapply_body(const Item& it, int tile, double* ws, double* sb, double (*red)[16]) {
+__device__ __forceinline__ void hqapply_body(const Item& it, int tile, double* ws, double* sb, double* stau) {
   const int n = it.n;
-  const int c0 = tile * 16;
+  const int c0 = tile * kHqCols;
   if (c0 >= n) return;
   double* base = ws + it.ws;
   const double* __restrict__ QV = base + (int64_t)kBufYS * n * n;
   const double* __restrict__ Up = base + (int64_t)kBufG * n * n;
   double* __restrict__ U = base + (int64_t)kBufU * n * n;
-  constexpr int ngrp = 16;
-  const int tid = threadIdx.x, col = tid & 15, grp = tid >> 4;
-  const int nc = min(16, n - c0);
-  for (int r = grp; r < n; r += ngrp) sb[r * 17 + col] = (col < nc) ? Up[(int64_t)r * n + c0 + col] : 0.0;
-  double vc[kPer], vn[kPer];
+  constexpr int kParts = 64 / kHqCols;
+  const int lane = threadIdx.x, col = lane % kHqCols, part = lane / kHqCols;
+  const int nc = min(kHqCols, n - c0);
+  auto sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+  for (int r = part; r < n; r += kParts) sb[r * kHqCols + col] = (col < nc) ? Up[(int64_t)r * n + c0 + col] : 0.0;
+  // Reflector k (n - k - 1 entries) is loaded kDepth steps before it is applied: its data was
+  // written by another workgroup, usually on another XCD, and a load takes about a step's time.
+  // The loads are unconditional (index clamped to the row; entries past the reflector are never
+  // used) so that the compiler can count them and wait only for the oldest; the taus are staged
+  // in LDS once.
+  constexpr int kDepth = kPer <= 16 ? 4 : 1;  // registers: (kDepth + 1) kPer doubles
+  double va[kDepth][kPer];
+  auto load = [&](int k, double* dst) {
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) vc[q] = vn[q] = 0.0;
-  double tau_n = 0.0;
-  if (n >= 3) {
+    for (int q = 0; q < kPer; ++q) dst[q] = QV[(int64_t)k * n + min(part + kParts * q, n - 1)];
+  };
+  for (int i = lane; i < n - 2; i += 64) stau[i] = QV[(int64_t)(n - 1) * n + i];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int i = grp + ngrp * q;
-      if (i < 2) vn[q] = QV[(int64_t)(n - 3) * n + i];
-    }
-    tau_n = QV[(int64_t)(n - 1) * n + n - 3];
-  }
-  __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    const double tau = tau_n;
-    const int len = n - k - 1;
+  for (int s = 0; s < kDepth; ++s) load(max(n - 3 - s, 0), va[s]);
+  sync();
+  for (int k0 = n - 3; k0 >= 0; k0 -= kDepth) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) vc[q] = vn[q];
-    if (k > 0) {
+    for (int s = 0; s < kDepth; ++s) {
+      const int k = k0 - s;
+      if (k < 0) break;
+      double vc[kPer];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) vc[q] = va[s][q];
+      load(max(k - kDepth, 0), va[s]);
+      const double tau = stau[k];
+      if (tau == 0.0) continue;  // uniform
+      const int len = n - k - 1;
+      double* u = sb + (k + 1) * kHqCols + col;
+      double w = 0.0;
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
-        const int i = grp + ngrp * q;
-        vn[q] = (i < len + 1) ? QV[(int64_t)(k - 1) * n + i] : 0.0;
+        const int i = part + kParts * q;
+        if (i < len) w += vc[q] * u[i * kHqCols];
       }
-      tau_n = QV[(int64_t)(n - 1) * n + k - 1];
-    }
-    if (tau == 0.0) continue;  // uniform
-    double w = 0.0;
+      for (int o = kHqCols; o < 64; o <<= 1) w += __shfl_xor(w, o);
+      w *= tau;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int i = grp + ngrp * q;
-      if (i < len) w += vc[q] * sb[(k + 1 + i) * 17 + col];
+      for (int q = 0; q < kPer; ++q) {
+        const int i = part + kParts * q;
+        if (i < len) u[i * kHqCols] -= vc[q] * w;
+      }
+      sync();  // the next reflector reads entries other lanes just wrote
     }
-    // the row groups of one wave differ in lane bits 4 and 5
-    w += __shfl_xor(w, 16);
-    w += __shfl_xor(w, 32);
-    if ((tid & 63) < 16) red[tid >> 6][col] = w;
-    __syncthreads();
-    w = (red[0][col] + red[1][col] + red[2][col] + red[3][col]) * tau;
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int i = grp + ngrp * q;
-      if (i < len) sb[(k + 1 + i) * 17 + col] -= vc[q] * w;
-    }
-    __syncthreads();
   }
   if (col < nc)
-    for (int r = grp; r < n; r += ngrp) U[(int64_t)r * n + c0 + col] = sb[r * 17 + col];
+    for (int r = part; r < n; r += kParts) U[(int64_t)r * n + c0 + col] = sb[r * kHqCols + col];
 }
 
-__global__ __launch_bounds__(256) void k_hqapply(const Item* items, int n_items, int tiles, double* ws,
-                                                  const int32_t* status) {
+__global__ __launch_bounds__(64) void k_hqapply(const Item* items, int n_items, int tiles, double* ws,
+                                                 const int32_t* status) {
   int g, tile;
   xcd_split(blockIdx.x, tiles, g, tile);  // the column blocks of one item share an XCD
   if (g >= n_items) return;
   const Item it = items[g];
   if (status[it.layer] != 0) return;
-  __shared__ double sb[kMaxn * 17];  // rows x 16 columns, row stride 17
-  __shared__ double red[4][16];
+  __shared__ double sb[kMaxn * kHqCols];  // rows x kHqCols columns
+  __shared__ double stau[kMaxn];          // tau_k of every reflector
   if (it.n <= 128)
-    hqapply_body<8>(it, tile, ws, sb, red);
+    hqapply_body<128 / (64 / kHqCols)>(it, tile, ws, sb, stau);
   else if (it.n <= 256)
-    hqapply_body<16>(it, tile, ws, sb, red);
+    hqapply_body<256 / (64 / kHqCols)>(it, tile, ws, sb, stau);
   else
-    hqapply_body<32>(it, tile, ws, sb, red);
+    hqapply_body<kMaxn / (64 / kHqCols)>(it, tile, ws, sb, stau);
 }
 
 }  // namespace vbrdf

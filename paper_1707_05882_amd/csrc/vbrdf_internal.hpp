@@ -74,6 +74,7 @@ __global__ void k_eigen(const Item* items, double* ws, int32_t* status);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
+constexpr int kHqCols = 4;  // columns per k_hqapply wave
 __global__ void k_hqapply(const Item* items, int n_items, int tiles, double* ws, const int32_t* status);
 __global__ void k_lu(const Item* items, double* ws, int32_t* status);
 __global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status);
