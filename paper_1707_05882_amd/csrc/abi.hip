@@ -281,7 +281,7 @@ static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const
   mark();
   k_validate<<<(p->n_layers + 63) / 64, 64, 0, s>>>(p->layers_d, p->n_layers, tau, omega, coef, layer_status);
   mark();
-  k_legendre<<<ni, 128, 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
+  k_legendre<<<ni, kLegThreads, 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
   mark();
   const int at = (mN + 15) / 16;
   k_assemble<<<dim3(at, at, ni), 256, 0, s>>>(p->items_d, p->layers_d, p->quad_d, omega, coef, p->ws_d, layer_status);

@@ -72,33 +72,35 @@ __device__ inline double wseq_value(WSeq& q, int l, double x) {
   return nxt;
 }
 
-// Legendre table per item: leg[(l * N + i) * 3 + {0,1,2}] = (Pb, R, T) of order m at mu_i. One
-// thread per node; launched with 128 threads (N <= 128).
-__global__ __launch_bounds__(128) void k_legendre(const Item* items, const Layer* layers, const double* quad,
-                                                  double* ws, const int32_t* status) {
+// Legendre table per item: leg[(l * N + i) * 3 + {0,1,2}] = (Pb, R, T) of order m at mu_i.
+// The three recurrences d_{m0}, d_{m2}, d_{m,-2} of a node run on three threads (thread =
+// 128 sequence + node, N <= 128): each writes its own slot, d_{m2} and d_{m,-2} into the R and T
+// slots, and after a barrier R = -(d_{m2} + d_{m,-2})/2 and T = -(d_{m2} - d_{m,-2})/2 are formed
+// in place. Launched with kLegThreads threads.
+__global__ __launch_bounds__(kLegThreads) void k_legendre(const Item* items, const Layer* layers,
+                                                          const double* quad, double* ws,
+                                                          const int32_t* status) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
   const Layer ly = layers[it.layer];
   const int N = it.N, L = it.L, m = it.m;
   double* leg = ws + it.ws + leg_off(it.n);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+  const int seq = threadIdx.x / 128, i = threadIdx.x % 128;
+  if (i < N) {
     const double x = quad[ly.quad_off + i];
-    WSeq s0{m, 0, m, 0.0, 0.0};
-    WSeq sp{m, 2, m > 2 ? m : 2, 0.0, 0.0};
-    WSeq sm{m, -2, m > 2 ? m : 2, 0.0, 0.0};
+    const int nn = seq == 0 ? 0 : (seq == 1 ? 2 : -2);
+    WSeq q{m, nn, seq == 0 ? m : (m > 2 ? m : 2), 0.0, 0.0};
     for (int l = 0; l < L; ++l) {
-      double pb = wseq_value(s0, l, x);
-      double dp = wseq_value(sp, l, x);
-      double dm = wseq_value(sm, l, x);
-      double* o = leg + ((int64_t)l * N + i) * 3;
-      if (l < m) {
-        o[0] = 0.0; o[1] = 0.0; o[2] = 0.0;
-      } else {
-        o[0] = pb;
-        o[1] = -0.5 * (dp + dm);
-        o[2] = -0.5 * (dp - dm);
-      }
+      const double d = wseq_value(q, l, x);
+      leg[((int64_t)l * N + i) * 3 + seq] = (l < m) ? 0.0 : d;
     }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < L * N; t += blockDim.x) {
+    double* o = leg + (int64_t)t * 3;
+    const double dp = o[1], dm = o[2];
+    o[1] = -0.5 * (dp + dm);
+    o[2] = -0.5 * (dp - dm);
   }
 }
 

@@ -64,6 +64,7 @@ constexpr int kSynthMaxPhi = 1024;  // azimuth samples per layer
 // ---- kernels (one translation unit each)
 __global__ void k_validate(const Layer* layers, int n_layers, const double* tau, const double* omega,
                            const double* coef, int32_t* status);
+constexpr int kLegThreads = 3 * 128;  // k_legendre: three recurrences x up to 128 nodes
 __global__ void k_legendre(const Item* items, const Layer* layers, const double* quad, double* ws,
                            const int32_t* status);
 __global__ void k_assemble(const Item* items, const Layer* layers, const double* quad, const double* omega,
