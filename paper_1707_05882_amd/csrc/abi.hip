@@ -279,7 +279,7 @@ static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const
     ++stage;
   };
   mark();
-  k_validate<<<(p->n_layers + 63) / 64, 64, 0, s>>>(p->layers_d, p->n_layers, tau, omega, coef, layer_status);
+  k_validate<<<p->n_layers, 64, 0, s>>>(p->layers_d, p->n_layers, tau, omega, coef, layer_status);
   mark();
   k_legendre<<<ni, kLegThreads, 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
   mark();

@@ -13,19 +13,24 @@
 
 namespace vbrdf {
 
-__global__ void k_validate(const Layer* layers, int n_layers, const double* tau, const double* omega,
-                           const double* coef, int32_t* status) {
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
+// Input checks per layer (one wave per layer, lanes striding over the coefficients): tau > 0 and
+// finite, 0 < omega <= 1, alpha_1 of degree 0 equal to 1, every coefficient finite.
+__global__ __launch_bounds__(64) void k_validate(const Layer* layers, int n_layers, const double* tau,
+                                                 const double* omega, const double* coef, int32_t* status) {
+  const int l = blockIdx.x;
   if (l >= n_layers) return;
   const Layer ly = layers[l];
-  int32_t st = 0;
-  double t = tau[l], w = omega[l];
+  const double* c = coef + ly.coef_off;
+  int bad = 0;
+  for (int k = threadIdx.x; k < 6 * ly.L; k += 64)
+    if (!isfinite(c[k])) bad = 1;
+  for (int o = 1; o < 64; o <<= 1) bad |= __shfl_xor(bad, o);
+  if (threadIdx.x != 0) return;
+  const double t = tau[l], w = omega[l];
+  int32_t st = bad ? -1 : 0;
   if (!(t > 0.0) || !isfinite(t)) st = -1;
   if (!(w > 0.0) || !(w <= 1.0)) st = -1;
-  const double* c = coef + ly.coef_off;
   if (!(fabs(c[0] - 1.0) <= 1e-12)) st = -1;
-  for (int k = 0; k < 6 * ly.L; ++k)
-    if (!isfinite(c[k])) st = -1;
   status[l] = st;
 }
 
