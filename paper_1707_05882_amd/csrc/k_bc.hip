@@ -213,6 +213,7 @@ __device__ __forceinline__ bool lu_factor(double* A, int64_t ld, int n, int* per
 
 constexpr int kLuLds = kLdsMaxn * (kLdsMaxn + 1);  // LDS matrix
 constexpr int kVfixLds = kLuLds + kLdsMaxn;          // LDS matrix and one work vector
+static_assert(kVfixLds >= 2 * 256, "the column-maximum partials of a 256-thread block fit");
 
 // Per-item scratch of the boundary solve, in the extras block: 1 / Uu_kk of S' and T'
 // (2 x n doubles) and the two pivot orders (2 x n int32 in n doubles).
@@ -389,11 +390,15 @@ __device__ __forceinline__ void vfix_body(const Item& it, double* base, int32_t*
   double* V = base + (int64_t)kBufG * n * n;
   const double* lre = base + extras_off(n);
   const double* lim = lre + n;
-  // ||E~||_inf
+  // ||E~||_inf: 16 lanes per row (coalesced), rows spread over the block
+  constexpr int kRowLanes = 16;
   double part = 0.0;
-  for (int r = tid; r < n; r += NT) {
+  for (int r0 = 0; r0 < n; r0 += NT / kRowLanes) {
+    const int r = r0 + tid / kRowLanes;
     double s = 0.0;
-    for (int c = 0; c < n; ++c) s += fabs(E[(int64_t)r * n + c]);
+    if (r < n)
+      for (int c = tid % kRowLanes; c < n; c += kRowLanes) s += fabs(E[(int64_t)r * n + c]);
+    for (int o = 1; o < kRowLanes; o <<= 1) s += __shfl_xor(s, o);
     part = fmax(part, s);
   }
   if (tid == 0) *enorm = 0.0;
@@ -410,15 +415,43 @@ __device__ __forceinline__ void vfix_body(const Item& it, double* base, int32_t*
   __syncthreads();
   const double en = *enorm;
   int any = 0;
-  for (int j = tid; j < n; j += NT) {
-    double nu = 0.0, nv = 0.0;
-    for (int r = 0; r < n; ++r) {
-      nu = fmax(nu, fabs(U[(int64_t)r * n + j]));
-      nv = fmax(nv, fabs(V[(int64_t)r * n + j]));
+  if (n <= NT) {
+    // column maxima of |U| and |V|: NT / n threads per column split its rows, partials in smem
+    const int pc = NT / n;
+    double* pu = smem;
+    double* pv = smem + pc * n;
+    if (tid < pc * n) {
+      const int j = tid % n, q = tid / n;
+      double nu = 0.0, nv = 0.0;
+      for (int r = q; r < n; r += pc) {
+        nu = fmax(nu, fabs(U[(int64_t)r * n + j]));
+        nv = fmax(nv, fabs(V[(int64_t)r * n + j]));
+      }
+      pu[q * n + j] = nu;
+      pv[q * n + j] = nv;
     }
-    const int f = (nv < kVfixRatio * en * nu) ? 1 : 0;
-    flag[j] = f;
-    any |= f;
+    __syncthreads();
+    for (int j = tid; j < n; j += NT) {
+      double nu = 0.0, nv = 0.0;
+      for (int q = 0; q < pc; ++q) {
+        nu = fmax(nu, pu[q * n + j]);
+        nv = fmax(nv, pv[q * n + j]);
+      }
+      const int f = (nv < kVfixRatio * en * nu) ? 1 : 0;
+      flag[j] = f;
+      any |= f;
+    }
+  } else {
+    for (int j = tid; j < n; j += NT) {
+      double nu = 0.0, nv = 0.0;
+      for (int r = 0; r < n; ++r) {
+        nu = fmax(nu, fabs(U[(int64_t)r * n + j]));
+        nv = fmax(nv, fabs(V[(int64_t)r * n + j]));
+      }
+      const int f = (nv < kVfixRatio * en * nu) ? 1 : 0;
+      flag[j] = f;
+      any |= f;
+    }
   }
   __syncthreads();
   // pairs are flagged together
