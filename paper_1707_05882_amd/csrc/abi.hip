@@ -207,7 +207,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       for (int q = 0; q < ly.N; ++q) tasks.push_back(SynthTask{l, i, q, 0});
     p->max_n = std::max(p->max_n, n);
     p->trsm_tiles = std::max(p->trsm_tiles, (n + kTrsmRows - 1) / kTrsmRows);
-    p->trsm_lds = std::max(p->trsm_lds, sizeof(double) * (size_t)n * (kTrsmLdb + 2));
+    p->trsm_lds = std::max(p->trsm_lds, sizeof(double) * (size_t)n * (trsm_ldb(n) + 2));
     p->max_N = std::max(p->max_N, ly.N);
     coef_off += 6 * (int64_t)ly.L;
     out_off += (int64_t)ly.N * ly.N * ly.n_dphi * 16;

@@ -269,22 +269,15 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
 // U (workgroups ordered so that the tiles of one matrix run on one XCD and share its L2). One wave:
 // kLpr = 64 / kTrsmRows lanes share a row (lane = kLpr row + part), each taking every kLpr-th term
 // of the row's dot products, combined by lane exchanges. The tile is kept in LDS as Bt[c][r] (row
-// stride kTrsmLdb). No workgroup barrier. With W = Y P:
+// stride trsm_ldb(n)). No workgroup barrier. With W = Y P:
 //   Z Uu = U :  Z_j = (U_j - sum_{c<j} Z_c Uu_cj) / Uu_jj      (j ascending)
 //   W L = Z  :  W_j = Z_j - sum_{c>j} W_c L_cj                 (j descending, unit L)
 // and Y[:, perm[j]] = W[:, j]. The factor column used at step j is the same for all rows: the
 // wave stages it in LDS while the loads of the next column are in flight.
-__global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status) {
-  int g, tile;
-  xcd_split(blockIdx.x, tiles, g, tile);  // g = 2 item + side; the tiles of one matrix share an XCD
-  if (g >= 2 * n_items) return;
-  const Item it = items[g >> 1];
-  if (status[it.layer] != 0) return;
+template <int ldb>
+__device__ __forceinline__ void trsm_tile(const Item& it, int which, int r0, double* ws) {
   const int n = it.n, lane = threadIdx.x;
   constexpr int R = kTrsmRows;
-  const int r0 = tile * R;
-  if (r0 >= n) return;
-  const int which = g & 1;
   double* base = ws + it.ws;
   const double* __restrict__ AT = base + (int64_t)(which == 0 ? kBufG : kBufF) * n * n;
   const double* __restrict__ U = base + (int64_t)kBufU * n * n;
@@ -292,9 +285,8 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
   double* ex = base + extras_off(n);
   const double* __restrict__ id = lu_invd(ex, n, which);
   const int* __restrict__ pm = lu_perm(ex, n, which);
-  // LDS: Bt [n][kTrsmLdb], then two factor-column buffers [2][n]
+  // LDS: Bt [n][ldb], then two factor-column buffers [2][n]
   HIP_DYNAMIC_SHARED(double, smem)
-  constexpr int ldb = kTrsmLdb;
   double* Bt = smem;
   double* cb = smem + (int64_t)n * ldb;
   const int nr = min(R, n - r0);
@@ -371,6 +363,21 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
     const int rr = t / n, c = t % n;
     Y[(int64_t)(r0 + rr) * n + pm[c]] = Bt[c * ldb + rr];
   }
+}
+
+__global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status) {
+  int g, tile;
+  xcd_split(blockIdx.x, tiles, g, tile);  // g = 2 item + side; the tiles of one matrix share an XCD
+  if (g >= 2 * n_items) return;
+  const Item it = items[g >> 1];
+  if (status[it.layer] != 0) return;
+  const int r0 = tile * kTrsmRows;
+  if (r0 >= it.n) return;
+  // the tile stride is a compile-time constant so that LDS offsets fold into the instructions
+  if (trsm_ldb(it.n) == kTrsmLdb)
+    trsm_tile<kTrsmLdb>(it, g & 1, r0, ws);
+  else
+    trsm_tile<kTrsmRows + 1>(it, g & 1, r0, ws);
 }
 
 // Columns of V = E~ U that lost more than ~7 digits to cancellation (the conservation mode of

@@ -80,13 +80,15 @@ __global__ void k_hqapply(const Item* items, int n_items, int tiles, double* ws,
 __global__ void k_lu(const Item* items, double* ws, int32_t* status);
 __global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status);
 // right-hand-side rows per right-division tile (one wave, 64 / kTrsmRows lanes per row; the tile takes
-// n x (kTrsmLdb + 2) doubles of LDS)
+// n x (trsm_ldb(n) + 2) doubles of LDS)
 constexpr int kTrsmRows = 8;
 // LDS row stride of the right-division tile, in doubles. A 64-bit LDS access is served 16 lanes
 // at a time over 32 banks: 8 parts x 2 rows at offsets 18 part + row = 2 part + row (mod 16) meet
-// 16 distinct bank pairs.
+// 16 distinct bank pairs. Above n = 128 the tile would then hold so much LDS that fewer tiles fit
+// on a CU, which costs more than the conflicts, so those sizes keep the dense stride.
 constexpr int kTrsmLdb = 18;
 static_assert(kTrsmLdb > kTrsmRows, "the tile row holds kTrsmRows entries");
+__host__ __device__ inline int trsm_ldb(int n) { return n <= kLdsMaxn ? kTrsmLdb : kTrsmRows + 1; }
 
 // XCD-aware launch order: workgroups are dealt round-robin to the 8 XCDs (each with its own L2),
 // so the `tiles` workgroups that read one matrix get linear ids that agree mod 8. For `groups`
