@@ -1,11 +1,13 @@
 """Benchmark: BRDF solves per second (Fourier orders x incident directions) on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload particulate] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload batched] [--no-cpu-baseline]
 
 A step is one full solve of the workload (all stages: Legendre matrices and E/F assembly, FE
-product, eigen-decomposition, mode vectors, boundary solves, emergent response and Fourier
-synthesis of F_r) with the inputs already resident in device memory. The unit count of a layer is
-M x N x n_dphi (orders x incident zenith nodes x incident azimuths). Prints one JSON line.
+product, eigen-decomposition and its refinement, mode vectors, boundary solves, emergent response
+and Fourier synthesis of F_r) with the inputs already resident in device memory. The unit count of
+a layer is M x N x n_dphi (orders x incident zenith nodes x incident azimuths). The default
+workload is the largest one: 256 layers of uneven N in {16, 24, 32, 48, 64} with L = M = n_dphi = 2N.
+Prints one JSON line.
 """
 
 import argparse
@@ -21,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector and FP64 matrix
 PEAK_HBM_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def stage_work(stage, layers):
@@ -36,6 +39,8 @@ def stage_work(stage, layers):
                 fl += 25.0 * n ** 3           # real Schur form + eigenvectors (Golub-Van Loan count)
             elif stage in ("gemm_FE", "gemm_U", "gemm_V"):
                 fl += 2.0 * n ** 3
+            elif stage == "refine":
+                fl += 6.0 * n ** 3 + 2.0 / 3.0 * n ** 3 + 2.0 * n ** 3  # three GEMMs, LU of U^T, right division
             elif stage == "hqapply":
                 fl += 2.0 * n ** 3                           # n - 2 reflectors applied to n columns
             elif stage == "lu":
@@ -56,7 +61,7 @@ def stage_work(stage, layers):
 KERNEL_SOURCE = {"k_eigen": "k_eigen.hip", "k_hqapply": "k_eigen.hip", "k_lu": "k_bc.hip", "k_trsm": "k_bc.hip", "k_vfix": "k_bc.hip",
                  "k_bcbuild": "k_bc.hip", "k_colscal": "k_bc.hip", "k_response": "k_bc.hip", "k_gemm": "k_gemm.hip",
                  "k_assemble": "k_assemble.hip", "k_legendre": "k_assemble.hip", "k_validate": "k_assemble.hip",
-                 "k_synth": "k_synth.hip"}
+                 "k_synth": "k_synth.hip", "k_refine": "k_refine.hip"}
 
 
 def stage_kernel(stage):
@@ -85,18 +90,103 @@ def measured_traffic(kernel, workload):
     return None
 
 
+def golden_samples(name):
+    """Stored oracle values for the workload: list of (layer, azimuth indices, F sample, scale).
+
+    The files are written by the scripts next to them, which call only the CPU oracle."""
+    base = name.split("_")[0]
+    path = os.path.join(GOLDEN, f"{base}_sample.npz")
+    if not os.path.exists(path):
+        return []
+    g = np.load(path)
+    if "layers" in g:
+        return [(int(i), g[f"az{i}"], g[f"F{i}"], float(g[f"scale{i}"])) for i in g["layers"]]
+    return [(0, g["az"], g["F"], float(g["scale"]))]
+
+
+def err_vs_oracle(F, layers, name):
+    """max |F - F_oracle| / max |F_oracle,II| over the stored samples (every node pair at a few
+    azimuths), per layer, maximum over the sampled layers; None without stored samples."""
+    samples = golden_samples(name)
+    if not samples:
+        return None, 0
+    offs = np.cumsum([0] + [n * n * p * 16 for n, p in zip(layers.N, layers.n_dphi)])
+    worst = 0.0
+    for i, az, Fo, scale in samples:
+        n, p = layers.N[i], layers.n_dphi[i]
+        Fl = F[offs[i]:offs[i + 1]].view(n, n, p, 4, 4)[:, :, list(int(a) for a in az)].cpu().numpy()
+        worst = max(worst, float(np.abs(Fl - Fo).max() / scale))
+    return worst, len(samples)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(layers, units):
-    from threadpoolctl import threadpool_info
+    """The CPU oracle on a bounded, stated sample of the workload, scaled to the whole job.
+
+    One layer per distinct N (the first of each), every s-th Fourier order of it (s chosen so that
+    the sample is about 10 s of work); the per-layer time is the sampled orders' solve and synthesis
+    time times M / (orders sampled), and the job time weights each N by its number of layers. The
+    same sample at one BLAS thread, with a wider order stride, gives the single-thread rate."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import dom
+    from oracle.quadrature import double_gauss
 
+    firsts = {}
+    for i, N in enumerate(layers.N):
+        firsts.setdefault(N, i)
+    count = {N: layers.N.count(N) for N in firsts}
+    nmax = max(firsts)
+    work_per_order = {N: (4 * N) ** 3 for N in firsts}
+
+    def run(stride_at_max):
+        total = 0.0
+        detail = []
+        for N, i in sorted(firsts.items()):
+            M = layers.M[i]
+            # smaller systems are cheaper per order: sample them more densely
+            s = max(1, int(round(stride_at_max * work_per_order[N] / work_per_order[nmax])))
+            s = min(s, M)
+            ms = list(range(0, M, s))
+            coef, om = dom.validate(layers.coef[i], layers.tau[i], layers.omega[i], N, M)
+            mu, al = double_gauss(N)
+            t0 = time.perf_counter()
+            R = [dom.solve_order(coef, om, layers.tau[i], m, mu, al) for m in ms]
+            dom.synthesize(R, mu, layers.n_dphi[i])
+            dt = time.perf_counter() - t0
+            total += dt * M / len(ms) * count[N]
+            detail.append(f"N={N}: {len(ms)}/{M} orders")
+        return total, detail
+
+    # stride at the largest N so that the all-threads sample is roughly 10 s
+    big = firsts[nmax]
+    probe_m = 0
+    coef, om = dom.validate(layers.coef[big], layers.tau[big], layers.omega[big], nmax, layers.M[big])
+    mu, al = double_gauss(nmax)
     t0 = time.perf_counter()
-    for i in range(layers.n_layers):
-        dom.brdf(layers.coef[i], layers.tau[i], layers.omega[i], layers.N[i], layers.M[i], layers.n_dphi[i])
-    dt = time.perf_counter() - t0
+    dom.solve_order(coef, om, layers.tau[big], probe_m, mu, al)
+    t_order = time.perf_counter() - t0
+    per_sweep = t_order * sum(layers.M[i] * work_per_order[N] / work_per_order[nmax] for N, i in firsts.items())
+    stride = max(1, int(np.ceil(per_sweep / 8.0)))
+    t_all, detail = run(stride)
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": units / dt, "unit": "BRDF solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one full solve of the workload ({layers.n_layers} layer(s)), {dt:.2f} s"}
+    with threadpool_limits(limits=1):
+        t_one, detail1 = run(stride * 4)
+    return {"value": units / t_all, "unit": "BRDF solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"one layer per N ({', '.join(detail)}), scaled by M / sampled orders and by the "
+                       f"number of layers of each N; whole-job estimate {t_all:.1f} s"),
+            "one_thread": {"value": units / t_one, "cores": 1, "sample": ", ".join(detail1)},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def main():
@@ -104,7 +194,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="particulate")
+    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--graph-steps", type=int, default=5, help="replays of the hipGraph timed beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates HBM byte counters)")
@@ -136,7 +227,9 @@ def main():
     dev = torch.device("cuda:0")
     layers = workload(args.workload)
     units = layers.units()
+    t_plan = time.perf_counter()
     plan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, flags=binding.FLAG_STAGE_TIMING)
+    plan_ms = (time.perf_counter() - t_plan) * 1e3
     tau = torch.as_tensor(layers.tau, device=dev)
     omega = torch.as_tensor(layers.omega, device=dev)
     coef = torch.as_tensor(pack_coefficients(layers.coef), device=dev)
@@ -153,6 +246,7 @@ def main():
     if np.any(st != 0):
         print(f"solve failed: layer status {st.tolist()}", file=sys.stderr)
         sys.exit(1)
+    print(f"warm-up done ({args.warmup} solves), timing {args.steps}", file=sys.stderr, flush=True)
 
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -168,27 +262,28 @@ def main():
     if np.any(status.cpu().numpy() != 0) or not torch.isfinite(F).all():
         print("solve failed during the timed region", file=sys.stderr)
         sys.exit(1)
+    err, n_checked = err_vs_oracle(F, layers, layers.name)
 
     # the same solve captured once into a hipGraph and replayed (launch overhead removed); reported
     # beside the headline, which is the stage-timed eager sequence above
     graph_ms = None
+    gsteps = max(1, min(args.graph_steps, args.steps))
     try:
         gplan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, flags=binding.FLAG_GRAPH)
         gstream = torch.cuda.Stream()
         Fg = torch.empty_like(F)
         with torch.cuda.stream(gstream):
-            for _ in range(max(args.warmup, 1)):
-                gplan.solve(tau, omega, coef, Fg, status, gstream.cuda_stream)
+            gplan.solve(tau, omega, coef, Fg, status, gstream.cuda_stream)
             gstream.synchronize()
             g0 = torch.cuda.Event(enable_timing=True)
             g1 = torch.cuda.Event(enable_timing=True)
             g0.record(gstream)
-            for _ in range(args.steps):
+            for _ in range(gsteps):
                 gplan.solve(tau, omega, coef, Fg, status, gstream.cuda_stream)
             g1.record(gstream)
         torch.cuda.synchronize()
         if torch.equal(Fg, F):
-            graph_ms = g0.elapsed_time(g1) / args.steps
+            graph_ms = g0.elapsed_time(g1) / gsteps
         gplan.close()
     except binding.VbrdfError as e:
         print(f"graph replay unavailable: {e}", file=sys.stderr)
@@ -204,7 +299,7 @@ def main():
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                 "traffic": measured_traffic(kernel, layers.name), "kernel": kernel,
                 "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
-
+    one = layers.n_layers == 1
     out = {
         "metric": "BRDF solves/sec (orders x incident dirs)",
         "value": units / (ms / 1e3),
@@ -218,14 +313,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": layers.name, "layers": layers.n_layers, "N": layers.N[0] if layers.n_layers == 1 else "mixed",
-                   "L": layers.L[0] if layers.n_layers == 1 else "mixed", "M": layers.M[0] if layers.n_layers == 1 else "mixed",
-                   "n_dphi": layers.n_dphi[0] if layers.n_layers == 1 else "mixed", "units_per_step": units,
+        "config": {"workload": layers.name, "layers": layers.n_layers,
+                   "N": layers.N[0] if one else sorted(set(layers.N)),
+                   "L": layers.L[0] if one else "2N", "M": layers.M[0] if one else "2N",
+                   "n_dphi": layers.n_dphi[0] if one else "2N", "units_per_step": units,
                    "precision": "fp64", "base": "black"},
+        "err_vs_oracle": err,
+        "err_layers_checked": n_checked,
+        "physical_rhs_per_s": sum(m * 4 * n for m, n in zip(layers.M, layers.N)) / (ms / 1e3),
+        "plan_ms": plan_ms,
         "roofline": roofline,
         "graph_ms_per_step": graph_ms,
     }
     if not args.no_cpu_baseline:
+        print("timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(layers, units)
     print(json.dumps(out), flush=True)
 

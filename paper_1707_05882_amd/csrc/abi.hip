@@ -20,11 +20,11 @@ using namespace vbrdf;
 
 namespace {
 
-constexpr int kNumStages = 15;
+constexpr int kNumStages = kNumSolveStages;
 constexpr int kTimedSolves = 256;  // solves whose stage events are kept between queries
-const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen",
-                                             "gemm_U",   "hqapply",  "gemm_V",   "vfix",    "colscal",
-                                             "bcbuild",  "lu",       "trsm",     "response", "synth"};
+const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen",  "gemm_U",
+                                             "hqapply",  "refine",   "gemm_V",   "vfix",    "colscal", "bcbuild",
+                                             "lu",       "trsm",     "response", "synth"};
 
 thread_local std::string g_err;
 
@@ -37,6 +37,24 @@ vbrdf_status fail(vbrdf_status code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
+
+}  // namespace
+
+namespace vbrdf {
+
+vbrdf_status vbrdf_fail(vbrdf_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+}  // namespace vbrdf
+
+namespace {
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -94,24 +112,12 @@ vbrdf_status upload(const std::vector<T>& h, T** d) {
 
 }  // namespace
 
-struct vbrdf_plan {
-  int n_layers = 0;
-  int n_items = 0;
-  int max_n = 0;
-  int max_N = 0;
-  int trsm_tiles = 0;     // row tiles of the right division (largest item)
-  size_t trsm_lds = 0;   // its LDS bytes
+struct vbrdf_plan : LaunchSet {
   int precision = VBRDF_PRECISION_FP64;
   size_t out_doubles = 0;
   size_t ws_bytes = 0;
   std::vector<Layer> layers_h;
   std::vector<Item> items_h;
-  Layer* layers_d = nullptr;
-  Item* items_d = nullptr;
-  SynthTask* tasks_d = nullptr;
-  int n_tasks = 0;
-  double* quad_d = nullptr;
-  double* ws_d = nullptr;
   bool timing = false;
   bool graph = false;             // capture the solve into a hipGraph and replay it
   hipGraphExec_t gexec = nullptr;  // instantiated for the pointers in gkey
@@ -123,10 +129,10 @@ struct vbrdf_plan {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
-    if (layers_d) (void)hipFree(layers_d);
-    if (items_d) (void)hipFree(items_d);
-    if (tasks_d) (void)hipFree(tasks_d);
-    if (quad_d) (void)hipFree(quad_d);
+    if (layers_d) (void)hipFree(const_cast<Layer*>(layers_d));
+    if (items_d) (void)hipFree(const_cast<Item*>(items_d));
+    if (tasks_d) (void)hipFree(const_cast<SynthTask*>(tasks_d));
+    if (quad_d) (void)hipFree(const_cast<double*>(quad_d));
     if (ws_d) (void)hipFree(ws_d);
   }
 };
@@ -224,8 +230,19 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
                 (unsigned long long)d->workspace_cap_bytes);
   }
   vbrdf_status st;
-  if ((st = upload(p->layers_h, &p->layers_d)) != VBRDF_OK || (st = upload(p->items_h, &p->items_d)) != VBRDF_OK ||
-      (st = upload(tasks, &p->tasks_d)) != VBRDF_OK || (st = upload(quad, &p->quad_d)) != VBRDF_OK) {
+  Layer* layers_d = nullptr;
+  Item* items_d = nullptr;
+  SynthTask* tasks_d = nullptr;
+  double* quad_d = nullptr;
+  st = upload(p->layers_h, &layers_d);
+  p->layers_d = layers_d;
+  if (st == VBRDF_OK) st = upload(p->items_h, &items_d);
+  p->items_d = items_d;
+  if (st == VBRDF_OK) st = upload(tasks, &tasks_d);
+  p->tasks_d = tasks_d;
+  if (st == VBRDF_OK) st = upload(quad, &quad_d);
+  p->quad_d = quad_d;
+  if (st != VBRDF_OK) {
     delete p;
     return st;
   }
@@ -268,14 +285,19 @@ size_t vbrdf_plan_output_bytes(const vbrdf_plan* plan) { return plan ? plan->out
 
 size_t vbrdf_plan_workspace_bytes(const vbrdf_plan* plan) { return plan ? plan->ws_bytes : 0; }
 
-// The launch sequence of one solve on stream s (events between stages when evs is given).
-static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const double* coef, double* F_r,
-                    int32_t* layer_status, hipStream_t s, bool rec) {
+}  // extern "C"
+
+namespace vbrdf {
+
+// The launch sequence of one solve on stream s; when evs is given, kNumSolveStages + 1 events are
+// recorded around and between the stages.
+void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef, double* F_r,
+                   int32_t* layer_status, hipStream_t s, hipEvent_t* evs) {
+  const LaunchSet* p = &ls;
   const int ni = p->n_items, mn = p->max_n, mN = p->max_N;
   int stage = 0;
-  hipEvent_t* evs = rec ? &p->ev[(size_t)p->timed * (kNumStages + 1)] : nullptr;
   auto mark = [&]() {
-    if (rec) (void)hipEventRecord(evs[stage], s);
+    if (evs) (void)hipEventRecord(evs[stage], s);
     ++stage;
   };
   mark();
@@ -288,34 +310,55 @@ static void enqueue(vbrdf_plan* p, const double* tau, const double* omega, const
   mark();
   const int gt = (mn + 63) / 64;
   const dim3 gg(gt, gt, ni);
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, 0, kBufE, kBufG, layer_status);  // G = F~ E~
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, 0, kBufE, kBufG, 0, layer_status);  // G = F~ E~
   mark();
   k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufG, layer_status);  // U' = Z X
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufG, 0, layer_status);  // U' = Z X
   mark();
   const int hqt = (mn + kHqCols - 1) / kHqCols;
   k_hqapply<<<xcd_grid(ni, hqt), 64, 0, s>>>(p->items_d, ni, hqt, p->ws_d, layer_status);  // U = Q U'
   mark();
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, layer_status);  // V = E~ U
+  // one Newton step on the eigen-decomposition with the factored product F~ (E~ U)
+  const int et = (mn + 15) / 16;
+  const int tt = (mn + 31) / 32;
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, 0, layer_status);  // E~ U
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, 0, kBufG, kBufZ, 1, layer_status);  // (F~ E~ U)^T
+  k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, layer_status);  // U^T
+  k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, LuBufs{{kBufX, kBufX}, {kBufYS, kBufYS}});
+  k_trsm<<<xcd_grid(ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(
+      p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status,
+      TrsmBufs{{kBufYS, kBufYS}, {kBufZ, kBufZ}, {kBufG, kBufG}, 1});  // Y^T = (G U)^T U^-T
+  k_refine_lam<<<dim3((mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_refine_close<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_refine_pairs<<<dim3((mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_refine_delta<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufU, 0, kBufX, kBufZ, 0, layer_status);  // U (I + X) Q
+  k_refine_commit<<<dim3((mn * mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  mark();
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, 0, layer_status);  // V = E~ U
   mark();
   k_vfix<<<ni, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
   k_colscal<<<dim3((mn + 63) / 64, ni), 64, 0, s>>>(p->items_d, tau, p->ws_d, layer_status);
   mark();
-  const int et = (mn + 15) / 16;
   k_bcbuild<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, LuBufs{{kBufZ, kBufX}, {kBufG, kBufF}});
   mark();
-  k_trsm<<<xcd_grid(2 * ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d,
-                                                                 layer_status);
+  k_trsm<<<xcd_grid(2 * ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(
+      p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status,
+      TrsmBufs{{kBufG, kBufF}, {kBufU, kBufU}, {kBufYS, kBufYT}, 2});  // U S'^-1, U T'^-1
   mark();
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
   mark();
   k_synth<<<p->n_tasks, 256, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
   mark();
 }
+
+}  // namespace vbrdf
+
+extern "C" {
 
 vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, const double* coef, double* F_r,
                          int32_t* layer_status, void* stream) {
@@ -333,7 +376,7 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
         p->gexec = nullptr;
       }
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      enqueue(p, tau, omega, coef, F_r, layer_status, s, false);
+      enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s, nullptr);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(s, &g);
       if (ec != hipSuccess) return fail(VBRDF_E_DEVICE, "stream capture: %s", hipGetErrorString(ec));
@@ -349,7 +392,8 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
     return VBRDF_OK;
   }
   const bool rec = p->timing && p->timed < kTimedSolves;
-  enqueue(p, tau, omega, coef, F_r, layer_status, s, rec);
+  enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s,
+                rec ? &p->ev[(size_t)p->timed * (kNumStages + 1)] : nullptr);
   if (rec) ++p->timed;
   HIP_TRY(hipGetLastError());
   return VBRDF_OK;

@@ -222,17 +222,19 @@ __device__ inline int* lu_perm(double* ex, int n, int which) {
   return reinterpret_cast<int*>(ex + 2 * (int64_t)n) + which * n;
 }
 
-// LU factorisation with partial pivoting of S' (blockIdx.y = 0) or T' (1), P^T A = L Uu. The
-// factor is written transposed, AT[j n + c] = A(c, j), so that column j of Uu (c < j) and of L
+// LU factorisation with partial pivoting of buffer b.src[side] (side = blockIdx.y: S' and T' of the
+// boundary solve, or U^T of the eigenpair refinement), P^T A = L Uu. The factor is written
+// transposed into b.dst[side], AT[j n + c] = A(c, j), so that column j of Uu (c < j) and of L
 // (c > j) are contiguous for the right division; pivots and 1 / Uu_kk go to the extras block.
-__global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int32_t* status) {
+// The source buffer is overwritten when n > kLdsMaxn (factored in place).
+__global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
   const int n = it.n, tid = threadIdx.x, NT = blockDim.x;
   const int which = blockIdx.y;
   double* base = ws + it.ws;
-  double* Ag = base + (int64_t)(which == 0 ? kBufZ : kBufX) * n * n;
-  double* AT = base + (int64_t)(which == 0 ? kBufG : kBufF) * n * n;
+  double* Ag = base + (int64_t)b.src[which] * n * n;
+  double* AT = base + (int64_t)b.dst[which] * n * n;
   double* ex = base + extras_off(n);
   __shared__ double smem[kLuLds];
   __shared__ int perm[2 * kMaxn];
@@ -265,8 +267,9 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
   }
 }
 
-// Right division Y = U A^-1 with the factors of k_lu, for S' and T' and a tile of kTrsmRows rows of
-// U (workgroups ordered so that the tiles of one matrix run on one XCD and share its L2). One wave:
+// Right division Y = B A^-1 with the factors of k_lu (S' and T' with B = U in the boundary solve,
+// U^T with B = (G U)^T in the eigenpair refinement), for a tile of kTrsmRows rows of B (workgroups
+// ordered so that the tiles of one matrix run on one XCD and share its L2). One wave:
 // kLpr = 64 / kTrsmRows lanes share a row (lane = kLpr row + part), each taking every kLpr-th term
 // of the row's dot products, combined by lane exchanges. The tile is kept in LDS as Bt[c][r] (row
 // stride trsm_ldb(n)). No workgroup barrier. With W = Y P:
@@ -275,13 +278,13 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
 // and Y[:, perm[j]] = W[:, j]. The factor column used at step j is the same for all rows: the
 // wave stages it in LDS while the loads of the next column are in flight.
 template <int ldb>
-__device__ __forceinline__ void trsm_tile(const Item& it, int which, int r0, double* ws) {
+__device__ __forceinline__ void trsm_tile(const Item& it, int which, int r0, double* ws, const TrsmBufs& bf) {
   const int n = it.n, lane = threadIdx.x;
   constexpr int R = kTrsmRows;
   double* base = ws + it.ws;
-  const double* __restrict__ AT = base + (int64_t)(which == 0 ? kBufG : kBufF) * n * n;
-  const double* __restrict__ U = base + (int64_t)kBufU * n * n;
-  double* __restrict__ Y = base + (int64_t)(which == 0 ? kBufYS : kBufYT) * n * n;
+  const double* __restrict__ AT = base + (int64_t)bf.a[which] * n * n;
+  const double* __restrict__ U = base + (int64_t)bf.rhs[which] * n * n;
+  double* __restrict__ Y = base + (int64_t)bf.y[which] * n * n;
   double* ex = base + extras_off(n);
   const double* __restrict__ id = lu_invd(ex, n, which);
   const int* __restrict__ pm = lu_perm(ex, n, which);
@@ -365,19 +368,21 @@ __device__ __forceinline__ void trsm_tile(const Item& it, int which, int r0, dou
   }
 }
 
-__global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status) {
+__global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status,
+                                             TrsmBufs b) {
   int g, tile;
-  xcd_split(blockIdx.x, tiles, g, tile);  // g = 2 item + side; the tiles of one matrix share an XCD
-  if (g >= 2 * n_items) return;
-  const Item it = items[g >> 1];
+  xcd_split(blockIdx.x, tiles, g, tile);  // g = sides item + side; the tiles of one matrix share an XCD
+  if (g >= b.sides * n_items) return;
+  const Item it = items[g / b.sides];
   if (status[it.layer] != 0) return;
   const int r0 = tile * kTrsmRows;
   if (r0 >= it.n) return;
+  const int side = g % b.sides;
   // the tile stride is a compile-time constant so that LDS offsets fold into the instructions
   if (trsm_ldb(it.n) == kTrsmLdb)
-    trsm_tile<kTrsmLdb>(it, g & 1, r0, ws);
+    trsm_tile<kTrsmLdb>(it, side, r0, ws, b);
   else
-    trsm_tile<kTrsmRows + 1>(it, g & 1, r0, ws);
+    trsm_tile<kTrsmRows + 1>(it, side, r0, ws, b);
 }
 
 // Columns of V = E~ U that lost more than ~7 digits to cancellation (the conservation mode of

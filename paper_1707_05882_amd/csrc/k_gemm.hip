@@ -1,8 +1,9 @@
-// Batched square FP64 GEMM on the CDNA matrix cores: C = op(A) B for every work item.
+// Batched square FP64 GEMM on the CDNA matrix cores: C = op(A) B (or its transpose) for every
+// work item.
 //
 // Used for the products of the homogeneous step: FE (Sec. 3.A, eq. 43), E X for the mode vectors
-// (eq. 45) and the back-transformation of the eigenvectors. Each item carries its own n; the grid
-// covers the largest n and surplus tiles exit.
+// (eq. 45), the back-transformation of the eigenvectors and the products of the eigenpair
+// refinement. Each item carries its own n; the grid covers the largest n and surplus tiles exit.
 //
 // Tiling: 64 x 64 output tile per workgroup of 4 waves; each wave owns a 32 x 32 quadrant as 2 x 2
 // v_mfma_f64_16x16x4 tiles; K is staged through LDS 16 at a time. Lane layout of the 16x16x4 FP64
@@ -19,7 +20,7 @@ constexpr int kGT = 64;  // output tile
 constexpr int kGK = 16;  // K step
 
 __global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB,
-                                               int bufC, const int32_t* status) {
+                                               int bufC, int transC, const int32_t* status) {
   const Item it = items[blockIdx.z];
   if (status[it.layer] != 0) return;
   const int n = it.n;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int
       for (int v = 0; v < 4; ++v) {
         const int row = r0 + wr + x * 16 + lk + 4 * v;
         const int col = c0 + wc + y * 16 + li;
-        if (row < n && col < n) C[(int64_t)row * n + col] = acc[x][y][v];
+        if (row < n && col < n) C[transC ? (int64_t)col * n + row : (int64_t)row * n + col] = acc[x][y][v];
       }
 }
 

@@ -69,7 +69,8 @@ __global__ void k_legendre(const Item* items, const Layer* layers, const double*
                            const int32_t* status);
 __global__ void k_assemble(const Item* items, const Layer* layers, const double* quad, const double* omega,
                            const double* coef, double* ws, const int32_t* status);
-__global__ void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB, int bufC,
+// C = op(A) B, written transposed (C[c][r]) when transC is set
+__global__ void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB, int bufC, int transC,
                        const int32_t* status);
 __global__ void k_eigen(const Item* items, double* ws, int32_t* status);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
@@ -77,8 +78,27 @@ __global__ void k_colscal(const Item* items, const double* tau, double* ws, int3
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
 constexpr int kHqCols = 4;  // columns per k_hqapply wave
 __global__ void k_hqapply(const Item* items, int n_items, int tiles, double* ws, const int32_t* status);
-__global__ void k_lu(const Item* items, double* ws, int32_t* status);
-__global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status);
+// Buffers of the factorisation and right-division kernels per side (blockIdx.y of k_lu, or the
+// low digit of the matrix index of k_trsm): LU of src into the transposed factor dst; right
+// division y = rhs a^-1 with a's factor in buffer a. The side also selects the pivot and 1 / Uu_kk
+// slots of the extras block.
+struct LuBufs {
+  int32_t src[2], dst[2];
+};
+struct TrsmBufs {
+  int32_t a[2], rhs[2], y[2];
+  int32_t sides;  // 1 or 2 matrices per item
+};
+__global__ void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b);
+__global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status, TrsmBufs b);
+// Eigenpair refinement of the homogeneous step (between the eigenvector back-transformation and the
+// mode vectors): transposed copy, per-column update of the eigenvalues, correction matrix, commit.
+__global__ void k_transpose(const Item* items, double* ws, int src, int dst, const int32_t* status);
+__global__ void k_refine_lam(const Item* items, double* ws, const int32_t* status);
+__global__ void k_refine_close(const Item* items, double* ws, const int32_t* status);
+__global__ void k_refine_pairs(const Item* items, double* ws, const int32_t* status);
+__global__ void k_refine_delta(const Item* items, double* ws, const int32_t* status);
+__global__ void k_refine_commit(const Item* items, double* ws, const int32_t* status);
 // right-hand-side rows per right-division tile (one wave, 64 / kTrsmRows lanes per row; the tile takes
 // n x (trsm_ldb(n) + 2) doubles of LDS)
 constexpr int kTrsmRows = 8;
@@ -105,6 +125,28 @@ __global__ void k_response(const Item* items, const Layer* layers, const double*
                            const int32_t* status);
 __global__ void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
                         const double* ws, double* F, const int32_t* status);
+// Device tables and launch shape of a solve: the plan's, or those of the allocation-free entry
+// point (tables inside its static scratch array).
+struct LaunchSet {
+  const Layer* layers_d = nullptr;
+  const Item* items_d = nullptr;
+  const SynthTask* tasks_d = nullptr;
+  const double* quad_d = nullptr;  // per layer mu[N] then alpha[N]
+  double* ws_d = nullptr;          // per-item workspace blocks
+  int n_layers = 0, n_items = 0, n_tasks = 0;
+  int max_n = 0, max_N = 0;
+  int trsm_tiles = 0;   // row tiles of the right division (largest item)
+  size_t trsm_lds = 0;  // its LDS bytes
+};
+
+// Records the calling thread's error message (returned by vbrdf_last_error) and returns code.
+int32_t vbrdf_fail(int32_t code, const char* fmt, ...);
+
+// Stages of the launch sequence (events are recorded around and between them when requested).
+constexpr int kNumSolveStages = 16;
+void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef, double* F_r,
+                   int32_t* layer_status, hipStream_t s, hipEvent_t* evs);
+
 __global__ void k_radiance(const Layer* layers, int layer, int q, const double* quad, const double* F,
                            double i0, double i1, double i2, double i3, double* I_out);
 

@@ -19,6 +19,14 @@ from workloads.layers import hg_like_coefficients
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
+# Per-order responses, relative to the largest |R^m| entry of the layer. The FP64 path forms
+# G = F~ E~, whose rounding (eps ||G||, ||G|| ~ 1/mu_min^2) cannot separate the eigenvalues of a
+# node's four Stokes components in orders where the scattering has almost died out (they split by
+# the order's scattering strength). Each such cluster's response is then off by up to
+# eps ||G|| / lambda_node of the cluster's weight, an absolute floor near 2e-10 at N = 32 and
+# below it at N = 128 (smaller weights); 1e-9 keeps a margin of five over it. The BRDF itself is
+# gated at TOL.
+TOL_ORDER = 1e-9
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -83,9 +91,9 @@ def test_particulate_eigenvalues(particulate):
 def test_particulate_orders(particulate):
     l, _, Ro, _, st, s = particulate
     scale = max(np.abs(R).max() for R in Ro)
-    for m in (0, 1, 2, 31, 62, 63):
+    for m in range(l["M"]):
         R, _ = s.plan.inspect(0, m)
-        assert np.abs(R - Ro[m]).max() < 2e-9 * scale, m  # intermediate: eps ||FE|| floor of the half-size eigenproblem
+        assert np.abs(R - Ro[m]).max() < TOL_ORDER * scale, m
 
 
 def test_particulate_brdf(particulate):
@@ -183,7 +191,7 @@ def test_stage_timing():
     st = torch.empty(1, dtype=torch.int32, device=dev)
     plan.solve(t, w, c, F, st, torch.cuda.current_stream().cuda_stream)
     times = plan.stage_times()
-    assert list(times) == ["validate", "legendre", "assemble", "gemm_FE", "eigen", "gemm_U", "hqapply", "gemm_V",
+    assert list(times) == ["validate", "legendre", "assemble", "gemm_FE", "eigen", "gemm_U", "hqapply", "refine", "gemm_V",
                            "vfix", "colscal", "bcbuild", "lu", "trsm", "response", "synth"]
     assert all(v >= 0 for v in times.values())
 
@@ -222,41 +230,55 @@ def test_graph_replay_matches_eager():
     assert float(junk) == float(junk)
 
 
-def test_large_workload_sampled_outputs():
+def _inspect_rows_cols(plan, layer, m, idx):
+    R, _ = plan.inspect(layer, m)
+    return R[idx, :], R[:, idx]
+
+
+def test_large_workload_every_node_pair():
     """The large workload (N = 128, 8N = 1024 per order, L = M = n_dphi = 256) at full size in the
-    bench's launch configuration, checked on a sample of F_r (every 16th i and q, every 32nd
-    azimuth) against oracle values stored by tests/golden/make_large_sample.py."""
+    bench's launch configuration: F_r of every (outgoing, incident) node pair, both ends of the mu
+    grid included, at four azimuth differences (cosine and sine blocks), and the per-order
+    responses R^m of orders 0, 1, 2, 64 and 255 on the rows and columns of nodes 0, 1, 63, 64, 126
+    and 127, against oracle values stored by tests/golden/make_large_sample.py."""
     import os
 
-    path = os.path.join(os.path.dirname(__file__), "golden", "large_sample.npz")
-    g = np.load(path)
-    si, sq, sk = (int(v) for v in g["strides"])
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "large_sample.npz"))
     w = workload("large")
     s = BRDFSolver(w.N, w.L, w.M, w.n_dphi)
     t, om, c = s.upload(w.tau, w.omega, w.coef)
     s.solve_device(t, om, c)
     torch.cuda.synchronize()
     assert s.status.cpu().tolist() == [0]
-    F = s.layer(0)[::si, ::sq, ::sk].cpu().numpy()
+    F = s.layer(0)[:, :, [int(k) for k in g["az"]]].cpu().numpy()
     assert np.isfinite(F).all()
     assert np.abs(F - g["F"]).max() / float(g["scale"]) < TOL
+    idx = g["idx"]
+    for k, m in enumerate(int(v) for v in g["orders"]):
+        rows, cols = _inspect_rows_cols(s.plan, 0, m, idx)
+        err = max(np.abs(rows - g["Rrows"][k]).max(), np.abs(cols - g["Rcols"][k]).max())
+        assert err < TOL_ORDER * float(g["Rscale"]), m
 
 
-def test_batched_workload_sampled_outputs():
+def test_batched_workload_one_layer_per_N():
     """The batched workload (256 layers of uneven N in {16, 24, 32, 48, 64}, L = M = n_dphi = 2N)
-    in one plan, as the bench would run it; every layer must succeed, and three layers (N = 48,
-    64, 16) are checked on a sample of F_r against oracle values stored by
-    tests/golden/make_batched_sample.py."""
+    in one plan, as the bench runs it; every layer must succeed. One layer of each N, and the
+    N = 64 layer of largest albedo, are checked on F_r for every node pair at four azimuth
+    differences and on R^m of orders 0, 1 and M - 1 (oracle values stored by
+    tests/golden/make_batched_sample.py)."""
     import os
 
     g = np.load(os.path.join(os.path.dirname(__file__), "golden", "batched_sample.npz"))
-    st_ = int(g["stride"])
     w = workload("batched")
     s = BRDFSolver(w.N, w.L, w.M, w.n_dphi)
     t, om, c = s.upload(w.tau, w.omega, w.coef)
     s.solve_device(t, om, c)
     torch.cuda.synchronize()
     assert (s.status.cpu().numpy() == 0).all()
+    assert sorted({w.N[int(i)] for i in g["layers"]}) == [16, 24, 32, 48, 64]
     for i in (int(v) for v in g["layers"]):
-        F = s.layer(i)[::st_, ::st_, ::st_].cpu().numpy()
+        F = s.layer(i)[:, :, [int(k) for k in g[f"az{i}"]]].cpu().numpy()
         assert np.abs(F - g[f"F{i}"]).max() / float(g[f"scale{i}"]) < TOL, i
+        for k, m in enumerate(int(v) for v in g[f"orders{i}"]):
+            R, _ = s.plan.inspect(i, m)
+            assert np.abs(R - g[f"R{i}"][k]).max() < TOL_ORDER * float(g[f"Rscale{i}"]), (i, m)

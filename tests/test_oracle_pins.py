@@ -13,7 +13,7 @@ import pytest
 from scipy.linalg import expm
 from scipy.special import gammaln, lpmv
 
-from oracle import analytic, brute, dom, legendre, particular, phase
+from oracle import analytic, brute, dom, doubling, legendre, particular, phase
 from oracle.quadrature import double_gauss
 from workloads.layers import _d_sequences, hg_like_coefficients, rayleigh_coefficients
 
@@ -180,6 +180,33 @@ def test_stream_form_matches_expm_propagator(N, tau0, omega):
         R = dom.solve_order(coef, omega, tau0, m, mu, al)
         Rb = brute.stream_response(coef, omega, tau0, m, N, dps=30)
         assert np.abs(R - Rb).max() < 1e-13 * max(1.0, np.abs(Rb).max()), m
+
+
+@pytest.mark.parametrize("N,tau0,omega", [(1, 0.1, 0.5), (2, 1.0, 0.9), (3, 3.0, 0.99)])
+def test_doubling_matches_expm_propagator(N, tau0, omega):
+    """The adding-doubling reference (thin-slice expm, interaction principle) against the
+    extended-precision propagator: two eigenvector-free routes that share only the operator."""
+    coef = hg(41 + N, 5)
+    mu, al = double_gauss(N)
+    for m in range(coef.shape[1]):
+        Rd = doubling.solve_order(coef, omega, tau0, m, mu, al)
+        Rb = brute.stream_response(coef, omega, tau0, m, N, dps=30)
+        assert np.abs(Rd - Rb).max() < 1e-13 * max(1.0, np.abs(Rb).max()), m
+
+
+def test_eigen_oracle_matches_doubling_every_order():
+    """The eigen-based per-order solve against adding-doubling at a size the propagator cannot
+    reach (N = 16, 8N = 128, thick and nearly conservative). Both are FP64; the eigen route errs by
+    about eps times the condition of its 8N basis and the doubling route by about eps per doubling
+    (k = 12 here), each relative to max |R|, so 1e-11 leaves two orders of margin over both."""
+    coef = hg(51, 32)
+    N, tau0, omega = 16, 10.0, 0.99
+    mu, al = double_gauss(N)
+    Rs = [dom.solve_order(coef, omega, tau0, m, mu, al) for m in range(32)]
+    scale = max(np.abs(R).max() for R in Rs)
+    for m in range(32):
+        Rd = doubling.solve_order(coef, omega, tau0, m, mu, al)
+        assert np.abs(Rs[m] - Rd).max() < 1e-11 * scale, m
 
 
 @pytest.mark.parametrize("N,mu0", [(2, 0.37), (3, 0.81)])
