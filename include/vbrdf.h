@@ -152,6 +152,28 @@ const char* vbrdf_stage_name(int32_t i);
 vbrdf_status vbrdf_radiance(const vbrdf_plan* plan, const double* F_r, int32_t layer, int32_t q,
                             const double I0[4], double* I_out, void* stream);
 
+/* Allocation-free solve of ONE layer, for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc). The same computation as
+ * a one-layer plan's vbrdf_solve, with the plan's tables and workspace replaced by a static device
+ * array of VBRDF_NOALLOC_SCRATCH_BYTES held by the library on every GPU it runs on until the
+ * process ends. Allocates nothing and copies nothing from the host: the tables, quadrature nodes
+ * included, are written by a set-up kernel on `stream`.
+ *   N, L, M, n_dphi          the layer's shape, as in vbrdf_plan_desc
+ *   tau, omega               device pointers to one double each
+ *   coef                     device doubles [6][L]
+ *   F_r                      device doubles [N][N][n_dphi][4][4]
+ *   layer_status             device int32 [1], written with VBRDF_OK or a negative code
+ * Enqueued on `stream`; returns after enqueueing. Errors: INVALID (null pointer, bad shape),
+ * UNSUPPORTED (N > VBRDF_MAX_N, M > 512, n_dphi > 1024), NOMEM (the layer's workspace, about
+ * 8 M (4N)^2 doubles, does not fit the static array: e.g. N = 32 fits up to M = 74, N = 64 up to
+ * M = 19), DEVICE. Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams or threads) race and must be serialised by the caller. Data-dependent problems
+ * are reported in layer_status exactly as by vbrdf_solve. */
+#define VBRDF_NOALLOC_SCRATCH_BYTES (80ull << 20)
+vbrdf_status vbrdf_solve_noalloc(int32_t N, int32_t L, int32_t M, int32_t n_dphi, const double* tau,
+                                 const double* omega, const double* coef, double* F_r, int32_t* layer_status,
+                                 void* stream);
+
 #ifdef __cplusplus
 }
 #endif

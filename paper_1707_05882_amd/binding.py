@@ -33,7 +33,9 @@ EXPORTED = (
     "vbrdf_abi_version", "vbrdf_last_error", "vbrdf_gauss_nodes", "vbrdf_plan_create",
     "vbrdf_plan_destroy", "vbrdf_plan_output_bytes", "vbrdf_plan_workspace_bytes", "vbrdf_solve",
     "vbrdf_plan_inspect", "vbrdf_radiance", "vbrdf_plan_stage_times", "vbrdf_stage_name",
+    "vbrdf_solve_noalloc",
 )
+NOALLOC_SCRATCH_BYTES = 80 << 20
 
 
 class VbrdfError(RuntimeError):
@@ -92,6 +94,8 @@ def load():
     L.vbrdf_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     L.vbrdf_stage_name.restype = ctypes.c_char_p
     L.vbrdf_stage_name.argtypes = [i32]
+    L.vbrdf_solve_noalloc.restype = i32
+    L.vbrdf_solve_noalloc.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
     if L.vbrdf_abi_version() != ABI_VERSION:
         raise OSError("libvbrdf.so ABI version mismatch")
     _lib = L
@@ -128,6 +132,12 @@ def gauss_nodes(N):
     dp = ctypes.POINTER(ctypes.c_double)
     _check(load().vbrdf_gauss_nodes(int(N), mu.ctypes.data_as(dp), al.ctypes.data_as(dp)))
     return mu, al
+
+
+def solve_noalloc(N, L, M, n_dphi, tau, omega, coef, F_r, layer_status, stream=0):
+    """One layer without device allocation (the library's static scratch array); device pointers."""
+    _check(load().vbrdf_solve_noalloc(int(N), int(L), int(M), int(n_dphi), _ptr(tau), _ptr(omega), _ptr(coef),
+                                      _ptr(F_r), _ptr(layer_status), ctypes.c_void_p(int(stream))))
 
 
 class Plan:
