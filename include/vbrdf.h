@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define VBRDF_ABI_VERSION 1
+#define VBRDF_ABI_VERSION 2
 
 typedef int32_t vbrdf_status;
 #define VBRDF_OK 0
@@ -50,9 +50,13 @@ typedef int32_t vbrdf_status;
 #define VBRDF_E_NOMEM (-3)       /* workspace above the cap, or device allocation failed */
 #define VBRDF_E_DEVICE (-4)      /* HIP runtime error (message kept in vbrdf_last_error) */
 #define VBRDF_E_NUMERIC (-5)     /* eigen iteration did not converge, zero pivot, NaN/Inf */
+#define VBRDF_E_NONCONVERGED (-6) /* FP32 refinement stalled and the FP64 fallback is disabled */
 
 /* Arithmetic of the per-order solves. */
 #define VBRDF_PRECISION_FP64 0
+/* Boundary factorisations and right divisions in FP32 on the matrix cores, recovered by iterative
+ * refinement against FP64 residuals (eigen-decomposition and products stay FP64). */
+#define VBRDF_PRECISION_FP32_REFINED 1
 
 /* Plan flags. */
 #define VBRDF_FLAG_STAGE_TIMING 1 /* record a hipEvent between the stages of every solve */
@@ -60,6 +64,12 @@ typedef int32_t vbrdf_status;
  * is captured again whenever the device pointers or the stream of a call differ from the previous
  * call's. Needs a non-default stream; cannot be combined with VBRDF_FLAG_STAGE_TIMING. */
 #define VBRDF_FLAG_GRAPH 2
+/* Keep the per-order diffuse-plus-direct transmission at the base (the downward field at tau0 for
+ * the same unit stream inputs, direct stream included) for vbrdf_plan_inspect. */
+#define VBRDF_FLAG_EMIT_TRANSMISSION 4
+/* FP32_REFINED only: report VBRDF_E_NONCONVERGED for a layer whose refinement stalls instead of
+ * redoing its boundary solve in FP64. */
+#define VBRDF_FLAG_DISABLE_FP64_FALLBACK 16
 
 /* Largest supported quadrature order per hemisphere (Stokes system size 4N = 512). */
 #define VBRDF_MAX_N 128
@@ -73,9 +83,18 @@ typedef struct vbrdf_plan_desc {
   const int32_t* L;          /* host [n_layers]: number of expansion coefficients, >= 1 */
   const int32_t* M;          /* host [n_layers]: Fourier orders m = 0..M-1, 1 <= M <= L */
   const int32_t* n_dphi;     /* host [n_layers]: azimuth samples, >= 1 */
-  int32_t precision;         /* VBRDF_PRECISION_FP64 */
-  int32_t flags;             /* 0, VBRDF_FLAG_STAGE_TIMING or VBRDF_FLAG_GRAPH */
+  int32_t precision;         /* VBRDF_PRECISION_FP64 or VBRDF_PRECISION_FP32_REFINED */
+  int32_t flags;             /* OR of VBRDF_FLAG_* (STAGE_TIMING and GRAPH exclude each other) */
   uint64_t workspace_cap_bytes; /* 0 = no cap; otherwise plan creation fails with NOMEM above it */
+  /* Optional caller-owned device workspace (256-byte aligned, at least vbrdf_workspace_query bytes)
+   * that the plan borrows instead of allocating its own; NULL = the plan allocates. It must stay
+   * valid until the plan is destroyed. */
+  void* workspace;
+  uint64_t workspace_bytes;
+  /* Largest number of QR sweeps per eigenproblem before the layer is reported NUMERIC; 0 = the
+   * default of 60 sweeps per row. A small cap forces the NUMERIC status (for tests). */
+  int32_t qr_sweep_cap;
+  int32_t reserved;          /* must be 0 */
 } vbrdf_plan_desc;
 
 /* ABI version of the loaded library (VBRDF_ABI_VERSION). */
@@ -97,6 +116,10 @@ vbrdf_status vbrdf_gauss_nodes(int32_t N, double* mu, double* alpha);
  * precision or flags),
  * NOMEM (cap exceeded or allocation failed), DEVICE. */
 vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* desc, vbrdf_plan** out);
+
+/* Device workspace, in bytes, that a plan for *desc needs (the size a caller-owned workspace must
+ * have). Host only. Errors as for vbrdf_plan_create's descriptor checks. */
+vbrdf_status vbrdf_workspace_query(const vbrdf_plan_desc* desc, uint64_t* bytes);
 
 /* Release the plan and its workspace. Waits for nothing: the caller must make sure no enqueued
  * solve still uses it. NULL is accepted. */
@@ -129,9 +152,12 @@ vbrdf_status vbrdf_solve(vbrdf_plan* plan, const double* tau, const double* omeg
  *   R_out[4N*4N]   emergent response R^m[(i,r),(q,p)]: Stokes r of the upward radiance at the
  *                  top on node i for a unit Stokes e_p entering on node q (order m), may be NULL
  *   lam_re[4N], lam_im[4N]   eigenvalues of FE (1/nu^2), may be NULL
+ *   T_out[4N*4N]   transmission T^m[(i,r),(q,p)]: Stokes r of the downward radiance at the base on
+ *                  node i for the same inputs, the attenuated incident stream included (plan created
+ *                  with VBRDF_FLAG_EMIT_TRANSMISSION; INVALID otherwise), may be NULL
  * Returns INVALID for an out-of-range layer or order. */
 vbrdf_status vbrdf_plan_inspect(const vbrdf_plan* plan, int32_t layer, int32_t m, double* R_out,
-                                double* lam_re, double* lam_im, void* stream);
+                                double* lam_re, double* lam_im, double* T_out, void* stream);
 
 /* Per-stage device times (milliseconds) of the solves enqueued on a plan created with
  * VBRDF_FLAG_STAGE_TIMING since the previous call (at most the first 256 of them), averaged per
@@ -145,11 +171,15 @@ int32_t vbrdf_plan_stage_times(vbrdf_plan* plan, float* ms_out, int32_t cap);
 /* Name of stage i (static string), or NULL when out of range. */
 const char* vbrdf_stage_name(int32_t i);
 
-/* Stokes radiances of eq. 1 from a solved F_r: for incidence I0 (4 Stokes) on node q at azimuth
- * phi0 = 0, I_out[i][k][r] = mu_q sum_p F_r[layer][i][q][k][r][p] I0[p], the upward radiance at
- * the top towards (-mu_i, dphi_k). F_r and I_out are device pointers (I_out: N*n_dphi*4 doubles),
- * I0 is a host array. Enqueued on `stream`. */
-vbrdf_status vbrdf_radiance(const vbrdf_plan* plan, const double* F_r, int32_t layer, int32_t q,
+/* Stokes radiances of eq. 1: for a beam of Stokes vector I0 (host array of 4) incident on node q
+ * at azimuth phi0 (radians), I_out[i][k][r] = mu_q sum_p F_r(i <- q, phi_k - phi0)[r][p] I0[p],
+ * the upward radiance at the top towards (-mu_i, phi_k = 2 pi k / n_dphi). When phi0 lies on the
+ * azimuth grid (a multiple of 2 pi / n_dphi within 1e-12 rad) the entries are read from the table
+ * F_r (device pointer, as written by vbrdf_solve); otherwise the Fourier series of eq. 12 is summed
+ * exactly at phi_k - phi0 from the per-order responses of the plan's last solve (valid until the
+ * next vbrdf_solve on this plan; F_r is then not read). I_out is a device pointer of N*n_dphi*4
+ * doubles. Enqueued on `stream`. */
+vbrdf_status vbrdf_radiance(const vbrdf_plan* plan, const double* F_r, int32_t layer, int32_t q, double phi0,
                             const double I0[4], double* I_out, void* stream);
 
 /* Allocation-free solve of ONE layer, for callers that cannot allocate device memory (code under

@@ -22,11 +22,11 @@ class BRDFSolver:
     F = solver(tau, omega, coefs)   # list of (N, N, n_dphi, 4, 4) float64 CUDA tensors
     """
 
-    def __init__(self, N, L, M, n_dphi, device="cuda"):
+    def __init__(self, N, L, M, n_dphi, device="cuda", precision=binding.PRECISION_FP64, flags=0, **plan_kw):
         if not torch.cuda.is_available():
             raise RuntimeError("BRDFSolver needs a ROCm GPU")
         self.device = torch.device(device)
-        self.plan = binding.Plan(N, L, M, n_dphi)
+        self.plan = binding.Plan(N, L, M, n_dphi, precision=precision, flags=flags, **plan_kw)
         sizes = self.plan.output_sizes()
         self.F = torch.empty(sum(sizes), dtype=torch.float64, device=self.device)
         self.status = torch.empty(self.plan.n_layers, dtype=torch.int32, device=self.device)
@@ -63,3 +63,26 @@ class BRDFSolver:
 
     def layer(self, i):
         return self._views[i]
+
+
+_PRECISIONS = {"fp64": binding.PRECISION_FP64, "fp32_refined": binding.PRECISION_FP32_REFINED}
+
+
+def brdf(tau, omega, coef, N, M, n_dphi, precision="fp64", device="cuda"):
+    """Polarized BRDF Mueller matrices of one or more layers on the Gauss-node grid.
+
+    tau, omega: scalars or sequences (one per layer); coef: a (6, L) array or a sequence of them;
+    N, M, n_dphi: ints or sequences. Returns a (N, N, n_dphi, 4, 4) float64 tensor on `device`
+    (outgoing node i, incident node q, azimuth difference 2 pi k / n_dphi, Mueller row, column),
+    or a list of them for several layers. Raises VbrdfError when a layer fails.
+    """
+    many = np.ndim(tau) > 0
+    taus = list(np.atleast_1d(np.asarray(tau, dtype=np.float64)))
+    oms = list(np.atleast_1d(np.asarray(omega, dtype=np.float64)))
+    coefs = list(coef) if many else [coef]
+    nl = len(taus)
+    per = lambda v: [int(x) for x in v] if np.ndim(v) > 0 else [int(v)] * nl
+    Ls = [np.asarray(c).shape[1] for c in coefs]
+    s = BRDFSolver(per(N), Ls, per(M), per(n_dphi), device=device, precision=_PRECISIONS[precision])
+    out = [v.clone() for v in s(taus, oms, coefs)]
+    return out if many else out[0]

@@ -20,22 +20,26 @@ E_UNSUPPORTED = -2
 E_NOMEM = -3
 E_DEVICE = -4
 E_NUMERIC = -5
+E_NONCONVERGED = -6
 PRECISION_FP64 = 0
+PRECISION_FP32_REFINED = 1
 FLAG_STAGE_TIMING = 1
 FLAG_GRAPH = 2
-ABI_VERSION = 1
+FLAG_EMIT_TRANSMISSION = 4
+FLAG_DISABLE_FP64_FALLBACK = 16
+ABI_VERSION = 2
 MAX_N = 128
+NOALLOC_SCRATCH_BYTES = 80 << 20
 
 STATUS_NAMES = {OK: "OK", E_INVALID: "INVALID", E_UNSUPPORTED: "UNSUPPORTED", E_NOMEM: "NOMEM",
-                E_DEVICE: "DEVICE", E_NUMERIC: "NUMERIC"}
+                E_DEVICE: "DEVICE", E_NUMERIC: "NUMERIC", E_NONCONVERGED: "NONCONVERGED"}
 
 EXPORTED = (
     "vbrdf_abi_version", "vbrdf_last_error", "vbrdf_gauss_nodes", "vbrdf_plan_create",
-    "vbrdf_plan_destroy", "vbrdf_plan_output_bytes", "vbrdf_plan_workspace_bytes", "vbrdf_solve",
-    "vbrdf_plan_inspect", "vbrdf_radiance", "vbrdf_plan_stage_times", "vbrdf_stage_name",
+    "vbrdf_workspace_query", "vbrdf_plan_destroy", "vbrdf_plan_output_bytes", "vbrdf_plan_workspace_bytes",
+    "vbrdf_solve", "vbrdf_plan_inspect", "vbrdf_radiance", "vbrdf_plan_stage_times", "vbrdf_stage_name",
     "vbrdf_solve_noalloc",
 )
-NOALLOC_SCRATCH_BYTES = 80 << 20
 
 
 class VbrdfError(RuntimeError):
@@ -55,6 +59,10 @@ class PlanDesc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("workspace_cap_bytes", ctypes.c_uint64),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_uint64),
+        ("qr_sweep_cap", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -78,6 +86,8 @@ def load():
     L.vbrdf_gauss_nodes.argtypes = [i32, dp, dp]
     L.vbrdf_plan_create.restype = i32
     L.vbrdf_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)]
+    L.vbrdf_workspace_query.restype = i32
+    L.vbrdf_workspace_query.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_uint64)]
     L.vbrdf_plan_destroy.restype = i32
     L.vbrdf_plan_destroy.argtypes = [vp]
     L.vbrdf_plan_output_bytes.restype = ctypes.c_size_t
@@ -87,9 +97,9 @@ def load():
     L.vbrdf_solve.restype = i32
     L.vbrdf_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.vbrdf_plan_inspect.restype = i32
-    L.vbrdf_plan_inspect.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.vbrdf_plan_inspect.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     L.vbrdf_radiance.restype = i32
-    L.vbrdf_radiance.argtypes = [vp, vp, i32, i32, dp, vp, vp]
+    L.vbrdf_radiance.argtypes = [vp, vp, i32, i32, ctypes.c_double, dp, vp, vp]
     L.vbrdf_plan_stage_times.restype = i32
     L.vbrdf_plan_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     L.vbrdf_stage_name.restype = ctypes.c_char_p
@@ -140,22 +150,49 @@ def solve_noalloc(N, L, M, n_dphi, tau, omega, coef, F_r, layer_status, stream=0
                                       _ptr(F_r), _ptr(layer_status), ctypes.c_void_p(int(stream))))
 
 
-class Plan:
-    """Owns a vbrdf_plan. Shapes are per-layer lists (or scalars for one layer)."""
+def _as_list(v):
+    return [int(x) for x in (v if hasattr(v, "__len__") else [v])]
 
-    def __init__(self, N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, workspace_cap_bytes=0):
-        as_list = lambda v: [int(x) for x in (v if hasattr(v, "__len__") else [v])]
-        self.N, self.L, self.M, self.n_dphi = (as_list(v) for v in (N, L, M, n_dphi))
+
+class _Desc:
+    """Keeps a PlanDesc and the shape arrays it points to alive together."""
+
+    def __init__(self, N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes,
+                 qr_sweep_cap):
+        self.N, self.L, self.M, self.n_dphi = (_as_list(v) for v in (N, L, M, n_dphi))
         nl = len(self.N)
         if not (len(self.L) == len(self.M) == len(self.n_dphi) == nl):
             raise ValueError("shape lists differ in length")
         arr = lambda v: (ctypes.c_int32 * nl)(*v)
-        self._keep = [arr(self.N), arr(self.L), arr(self.M), arr(self.n_dphi)]
-        desc = PlanDesc(ABI_VERSION, nl, *self._keep, int(precision), int(flags), int(workspace_cap_bytes))
-        h = ctypes.c_void_p()
-        _check(load().vbrdf_plan_create(ctypes.byref(desc), ctypes.byref(h)))
-        self._h = h
+        self.keep = [arr(self.N), arr(self.L), arr(self.M), arr(self.n_dphi)]
+        ws = _ptr(workspace) if workspace is not None else None
+        self.desc = PlanDesc(ABI_VERSION, nl, *self.keep, int(precision), int(flags), int(workspace_cap_bytes),
+                             ws, int(workspace_bytes), int(qr_sweep_cap), 0)
         self.n_layers = nl
+
+
+def workspace_query(N, L, M, n_dphi, precision=PRECISION_FP64, flags=0):
+    """Bytes of device workspace a plan of these shapes needs (host call)."""
+    d = _Desc(N, L, M, n_dphi, precision, flags, 0, None, 0, 0)
+    out = ctypes.c_uint64()
+    _check(load().vbrdf_workspace_query(ctypes.byref(d.desc), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Plan:
+    """Owns a vbrdf_plan. Shapes are per-layer lists (or scalars for one layer)."""
+
+    def __init__(self, N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, workspace_cap_bytes=0,
+                 workspace=None, workspace_bytes=0, qr_sweep_cap=0):
+        d = _Desc(N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes, qr_sweep_cap)
+        self.N, self.L, self.M, self.n_dphi = d.N, d.L, d.M, d.n_dphi
+        self.flags = int(flags)
+        self.precision = int(precision)
+        self._workspace = workspace  # the caller's buffer must outlive the plan
+        h = ctypes.c_void_p()
+        _check(load().vbrdf_plan_create(ctypes.byref(d.desc), ctypes.byref(h)))
+        self._h = h
+        self.n_layers = d.n_layers
 
     @property
     def handle(self):
@@ -174,14 +211,18 @@ class Plan:
         _check(load().vbrdf_solve(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(F_r), _ptr(layer_status),
                                   ctypes.c_void_p(int(stream))))
 
-    def inspect(self, layer, m, stream=0):
-        """Host copies of R^m (4N x 4N) and the eigenvalues of FE for one (layer, order)."""
+    def inspect(self, layer, m, stream=0, transmission=False):
+        """Host copies of R^m (4N x 4N) and the eigenvalues of FE for one (layer, order); with
+        transmission=True also T^m (plan created with FLAG_EMIT_TRANSMISSION)."""
         n = 4 * self.N[layer]
         R = np.zeros((n, n))
         lr = np.zeros(n)
         li = np.zeros(n)
-        _check(load().vbrdf_plan_inspect(self._h, int(layer), int(m), _ptr(R), _ptr(lr), _ptr(li),
+        T = np.zeros((n, n)) if transmission else None
+        _check(load().vbrdf_plan_inspect(self._h, int(layer), int(m), _ptr(R), _ptr(lr), _ptr(li), _ptr(T),
                                          ctypes.c_void_p(int(stream))))
+        if transmission:
+            return R, lr + 1j * li, T
         return R, lr + 1j * li
 
     def stage_times(self):
@@ -192,9 +233,9 @@ class Plan:
             _check(n)
         return {load().vbrdf_stage_name(i).decode(): float(buf[i]) for i in range(n)}
 
-    def radiance(self, F_r, layer, q, I0, I_out, stream=0):
+    def radiance(self, F_r, layer, q, I0, I_out, stream=0, phi0=0.0):
         i0 = (ctypes.c_double * 4)(*[float(v) for v in I0])
-        _check(load().vbrdf_radiance(self._h, _ptr(F_r), int(layer), int(q), i0, _ptr(I_out),
+        _check(load().vbrdf_radiance(self._h, _ptr(F_r), int(layer), int(q), float(phi0), i0, _ptr(I_out),
                                      ctypes.c_void_p(int(stream))))
 
     def close(self):

@@ -113,11 +113,11 @@ vbrdf_status upload(const std::vector<T>& h, T** d) {
 }  // namespace
 
 struct vbrdf_plan : LaunchSet {
-  int precision = VBRDF_PRECISION_FP64;
   size_t out_doubles = 0;
   size_t ws_bytes = 0;
   std::vector<Layer> layers_h;
   std::vector<Item> items_h;
+  bool ws_owned = true;  // false when the workspace is the caller's
   bool timing = false;
   bool graph = false;             // capture the solve into a hipGraph and replay it
   hipGraphExec_t gexec = nullptr;  // instantiated for the pointers in gkey
@@ -133,7 +133,7 @@ struct vbrdf_plan : LaunchSet {
     if (items_d) (void)hipFree(const_cast<Item*>(items_d));
     if (tasks_d) (void)hipFree(const_cast<SynthTask*>(tasks_d));
     if (quad_d) (void)hipFree(const_cast<double*>(quad_d));
-    if (ws_d) (void)hipFree(ws_d);
+    if (ws_d && ws_owned) (void)hipFree(ws_d);
   }
 };
 
@@ -155,19 +155,27 @@ vbrdf_status vbrdf_gauss_nodes(int32_t N, double* mu, double* alpha) {
   return VBRDF_OK;
 }
 
-vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
-  if (!out) return fail(VBRDF_E_INVALID, "null plan output pointer");
-  *out = nullptr;
+// Descriptor checks shared by plan creation and the workspace query.
+static vbrdf_status check_desc(const vbrdf_plan_desc* d) {
   if (!d) return fail(VBRDF_E_INVALID, "null plan descriptor");
   if (d->abi_version != VBRDF_ABI_VERSION)
     return fail(VBRDF_E_INVALID, "abi_version %d does not match library %d", d->abi_version, VBRDF_ABI_VERSION);
   if (d->n_layers < 1) return fail(VBRDF_E_INVALID, "n_layers must be >= 1");
   if (!d->N || !d->L || !d->M || !d->n_dphi) return fail(VBRDF_E_INVALID, "null shape array");
-  if (d->precision != VBRDF_PRECISION_FP64) return fail(VBRDF_E_UNSUPPORTED, "unknown precision %d", d->precision);
-  if (d->flags & ~(VBRDF_FLAG_STAGE_TIMING | VBRDF_FLAG_GRAPH))
-    return fail(VBRDF_E_UNSUPPORTED, "unknown flags 0x%x", d->flags);
+  if (d->precision != VBRDF_PRECISION_FP64 && d->precision != VBRDF_PRECISION_FP32_REFINED)
+    return fail(VBRDF_E_UNSUPPORTED, "unknown precision %d", d->precision);
+  const int known = VBRDF_FLAG_STAGE_TIMING | VBRDF_FLAG_GRAPH | VBRDF_FLAG_EMIT_TRANSMISSION |
+                    VBRDF_FLAG_DISABLE_FP64_FALLBACK;
+  if (d->flags & ~known) return fail(VBRDF_E_UNSUPPORTED, "unknown flags 0x%x", d->flags);
   if ((d->flags & VBRDF_FLAG_STAGE_TIMING) && (d->flags & VBRDF_FLAG_GRAPH))
     return fail(VBRDF_E_UNSUPPORTED, "stage timing and graph replay cannot be combined");
+  if ((d->flags & VBRDF_FLAG_DISABLE_FP64_FALLBACK) && d->precision != VBRDF_PRECISION_FP32_REFINED)
+    return fail(VBRDF_E_INVALID, "DISABLE_FP64_FALLBACK needs the FP32_REFINED precision");
+  if (d->qr_sweep_cap < 0) return fail(VBRDF_E_INVALID, "qr_sweep_cap must be >= 0 (got %d)", d->qr_sweep_cap);
+  if (d->reserved != 0) return fail(VBRDF_E_INVALID, "reserved descriptor field must be 0");
+  if (d->workspace_bytes && !d->workspace) return fail(VBRDF_E_INVALID, "workspace_bytes given without a workspace");
+  if (d->workspace && (reinterpret_cast<uintptr_t>(d->workspace) & 255))
+    return fail(VBRDF_E_INVALID, "caller workspace must be 256-byte aligned");
   for (int l = 0; l < d->n_layers; ++l) {
     const int N = d->N[l], L = d->L[l], M = d->M[l], P = d->n_dphi[l];
     if (N < 1 || L < 1 || M < 1 || P < 1) return fail(VBRDF_E_INVALID, "layer %d: N, L, M, n_dphi must be >= 1", l);
@@ -176,6 +184,28 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     if (M > kSynthMaxM) return fail(VBRDF_E_UNSUPPORTED, "layer %d: M = %d above %d", l, M, kSynthMaxM);
     if (P > kSynthMaxPhi) return fail(VBRDF_E_UNSUPPORTED, "layer %d: n_dphi = %d above %d", l, P, kSynthMaxPhi);
   }
+  return VBRDF_OK;
+}
+
+// Per-item workspace blocks, 256-byte aligned.
+static int64_t block_doubles(int N, int L) { return (item_doubles(4 * N, N, L) + 31) / 32 * 32; }
+
+vbrdf_status vbrdf_workspace_query(const vbrdf_plan_desc* d, uint64_t* bytes) {
+  if (!bytes) return fail(VBRDF_E_INVALID, "null output pointer");
+  *bytes = 0;
+  const vbrdf_status st = check_desc(d);
+  if (st != VBRDF_OK) return st;
+  int64_t total = 0;
+  for (int l = 0; l < d->n_layers; ++l) total += (int64_t)d->M[l] * block_doubles(d->N[l], d->L[l]);
+  *bytes = (uint64_t)total * sizeof(double);
+  return VBRDF_OK;
+}
+
+vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
+  if (!out) return fail(VBRDF_E_INVALID, "null plan output pointer");
+  *out = nullptr;
+  const vbrdf_status chk = check_desc(d);
+  if (chk != VBRDF_OK) return chk;
 
   vbrdf_plan* p = new (std::nothrow) vbrdf_plan();
   if (!p) return fail(VBRDF_E_NOMEM, "host allocation failed");
@@ -206,7 +236,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       it.L = ly.L;
       it.n = n;
       it.ws = ws_off;
-      ws_off += (item_doubles(n, ly.N, ly.L) + 31) / 32 * 32;  // 256-byte aligned blocks
+      ws_off += block_doubles(ly.N, ly.L);
       p->items_h.push_back(it);
     }
     for (int i = 0; i < ly.N; ++i)
@@ -229,6 +259,12 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     return fail(VBRDF_E_NOMEM, "workspace %zu bytes exceeds the cap %llu", need,
                 (unsigned long long)d->workspace_cap_bytes);
   }
+  if (d->workspace && d->workspace_bytes < p->ws_bytes) {
+    size_t need = p->ws_bytes;
+    delete p;
+    return fail(VBRDF_E_NOMEM, "caller workspace of %llu bytes is below the %zu bytes needed",
+                (unsigned long long)d->workspace_bytes, need);
+  }
   vbrdf_status st;
   Layer* layers_d = nullptr;
   Item* items_d = nullptr;
@@ -247,6 +283,9 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     return st;
   }
   p->graph = (d->flags & VBRDF_FLAG_GRAPH) != 0;
+  p->precision = d->precision;
+  p->transmission = (d->flags & VBRDF_FLAG_EMIT_TRANSMISSION) != 0;
+  p->qr_sweep_cap = d->qr_sweep_cap;
   if (d->flags & VBRDF_FLAG_STAGE_TIMING) {
     p->timing = true;
     p->ev.assign((size_t)kTimedSolves * (kNumStages + 1), nullptr);
@@ -266,11 +305,17 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       return fail(VBRDF_E_DEVICE, "hipFuncSetAttribute(k_trsm): %s", hipGetErrorString(ea));
     }
   }
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->ws_d), p->ws_bytes);
-  if (e != hipSuccess) {
-    size_t need = p->ws_bytes;
-    delete p;
-    return fail(VBRDF_E_NOMEM, "workspace allocation of %zu bytes failed: %s", need, hipGetErrorString(e));
+  if (d->workspace) {
+    p->ws_d = static_cast<double*>(d->workspace);
+    p->ws_owned = false;
+  } else {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->ws_d), p->ws_bytes);
+    if (e != hipSuccess) {
+      size_t need = p->ws_bytes;
+      p->ws_d = nullptr;
+      delete p;
+      return fail(VBRDF_E_NOMEM, "workspace allocation of %zu bytes failed: %s", need, hipGetErrorString(e));
+    }
   }
   *out = p;
   return VBRDF_OK;
@@ -312,7 +357,7 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   const dim3 gg(gt, gt, ni);
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, 0, kBufE, kBufG, 0, layer_status);  // G = F~ E~
   mark();
-  k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap);
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufG, 0, layer_status);  // U' = Z X
   mark();
@@ -350,7 +395,8 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
       p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status,
       TrsmBufs{{kBufG, kBufF}, {kBufU, kBufU}, {kBufYS, kBufYT}, 2});  // U S'^-1, U T'^-1
   mark();
-  k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status);
+  k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status,
+                                                       p->transmission ? 1 : 0);
   mark();
   k_synth<<<p->n_tasks, 256, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
   mark();
@@ -400,7 +446,7 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
 }
 
 vbrdf_status vbrdf_plan_inspect(const vbrdf_plan* p, int32_t layer, int32_t m, double* R_out, double* lam_re,
-                                double* lam_im, void* stream) {
+                                double* lam_im, double* T_out, void* stream) {
   if (!p) return fail(VBRDF_E_INVALID, "null plan");
   if (layer < 0 || layer >= p->n_layers) return fail(VBRDF_E_INVALID, "layer %d out of range", layer);
   const Layer& ly = p->layers_h[layer];
@@ -412,6 +458,10 @@ vbrdf_status vbrdf_plan_inspect(const vbrdf_plan* p, int32_t layer, int32_t m, d
   if (R_out) HIP_TRY(hipMemcpy(R_out, base + (int64_t)kBufE * n * n, sizeof(double) * n * n, hipMemcpyDeviceToHost));
   if (lam_re) HIP_TRY(hipMemcpy(lam_re, base + extras_off(n), sizeof(double) * n, hipMemcpyDeviceToHost));
   if (lam_im) HIP_TRY(hipMemcpy(lam_im, base + extras_off(n) + n, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (T_out) {
+    if (!p->transmission) return fail(VBRDF_E_INVALID, "the plan was created without EMIT_TRANSMISSION");
+    HIP_TRY(hipMemcpy(T_out, base + (int64_t)kBufF * n * n, sizeof(double) * n * n, hipMemcpyDeviceToHost));
+  }
   return VBRDF_OK;
 }
 
@@ -436,16 +486,28 @@ int32_t vbrdf_plan_stage_times(vbrdf_plan* p, float* ms_out, int32_t cap) {
 
 const char* vbrdf_stage_name(int32_t i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : nullptr; }
 
-vbrdf_status vbrdf_radiance(const vbrdf_plan* p, const double* F_r, int32_t layer, int32_t q, const double I0[4],
-                            double* I_out, void* stream) {
+vbrdf_status vbrdf_radiance(const vbrdf_plan* p, const double* F_r, int32_t layer, int32_t q, double phi0,
+                            const double I0[4], double* I_out, void* stream) {
   if (!p) return fail(VBRDF_E_INVALID, "null plan");
-  if (!F_r || !I0 || !I_out) return fail(VBRDF_E_INVALID, "null pointer");
+  if (!I0 || !I_out) return fail(VBRDF_E_INVALID, "null pointer");
   if (layer < 0 || layer >= p->n_layers) return fail(VBRDF_E_INVALID, "layer %d out of range", layer);
   const Layer& ly = p->layers_h[layer];
   if (q < 0 || q >= ly.N) return fail(VBRDF_E_INVALID, "incident node %d out of range", q);
+  if (!std::isfinite(phi0)) return fail(VBRDF_E_INVALID, "phi0 must be finite");
   const int total = ly.N * ly.n_dphi * 4;
-  k_radiance<<<(total + 255) / 256, 256, 0, reinterpret_cast<hipStream_t>(stream)>>>(
-      p->layers_d, layer, q, p->quad_d, F_r, I0[0], I0[1], I0[2], I0[3], I_out);
+  const double two_pi = 6.283185307179586;
+  const double steps = phi0 / two_pi * ly.n_dphi;
+  const double kr = std::nearbyint(steps);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (std::fabs(steps - kr) * two_pi / ly.n_dphi <= 1e-12) {  // on the grid: read the table
+    if (!F_r) return fail(VBRDF_E_INVALID, "null F_r");
+    const int kshift = (int)(((long long)kr % ly.n_dphi + ly.n_dphi) % ly.n_dphi);
+    k_radiance<<<(total + 255) / 256, 256, 0, s>>>(p->layers_d, layer, q, kshift, p->quad_d, F_r, I0[0], I0[1],
+                                                   I0[2], I0[3], I_out);
+  } else {
+    k_radiance_series<<<(total + 255) / 256, 256, 0, s>>>(p->layers_d, p->items_d, layer, q, phi0, p->ws_d, I0[0],
+                                                          I0[1], I0[2], I0[3], I_out);
+  }
   HIP_TRY(hipGetLastError());
   return VBRDF_OK;
 }

@@ -549,9 +549,11 @@ __global__ __launch_bounds__(256) void k_vfix(const Item* items, double* ws, int
     vfix_body<false>(it, base, status, smem, perm, invd, redv, redi, flag, &enorm);
 }
 
-// R^m = Delta (Y_S + Y_T - I) R0, written over kBufE.
+// R^m = Delta (Y_S + Y_T - I) R0, written over kBufE. With `transmission`, also the downward
+// field at the base for the same inputs, T^m = (Y_S - Y_T) R0 (the attenuated incident stream
+// included: in the stream form the total field is what the boundary solve returns), over kBufF.
 __global__ void k_response(const Item* items, const Layer* layers, const double* quad, double* ws,
-                           const int32_t* status) {
+                           const int32_t* status, int transmission) {
   const Item it = items[blockIdx.z];
   if (status[it.layer] != 0) return;
   const int n = it.n;
@@ -561,10 +563,13 @@ __global__ void k_response(const Item* items, const Layer* layers, const double*
   const Layer ly = layers[it.layer];
   double* base = ws + it.ws;
   const int64_t idx = (int64_t)a * n + b;
-  const double y = base[(int64_t)kBufYS * n * n + idx] + base[(int64_t)kBufYT * n * n + idx] - (a == b ? 1.0 : 0.0);
+  const double ys = base[(int64_t)kBufYS * n * n + idx], yt = base[(int64_t)kBufYT * n * n + idx];
+  const double y = ys + yt - (a == b ? 1.0 : 0.0);
   const double alq = quad[ly.quad_off + it.N + b / 4];
   const double sgn = ((a & 3) >= 2) ? -1.0 : 1.0;
-  base[(int64_t)kBufE * n * n + idx] = sgn * y / (3.141592653589793 * alq);
+  const double r0 = 1.0 / (3.141592653589793 * alq);
+  base[(int64_t)kBufE * n * n + idx] = sgn * y * r0;
+  if (transmission) base[(int64_t)kBufF * n * n + idx] = (ys - yt) * r0;
 }
 
 }  // namespace vbrdf

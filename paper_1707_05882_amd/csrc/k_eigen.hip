@@ -183,7 +183,7 @@ __device__ inline int hess_line(int tid, int P, int NT) {
 
 template <bool kLds>
 __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t* status, double* sH, double* srefl,
-                                           double* sred, int* sctl, double* sxyz, ZOp* zops) {
+                                           double* sred, int* sctl, double* sxyz, ZOp* zops, int sweep_cap) {
   const int n = it.n;
   double* G = base + (int64_t)kBufG * n * n;
   double* __restrict__ ZT = base + (int64_t)kBufZ * n * n;  // Z(r, c) = ZT[c * n + r]
@@ -393,7 +393,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
           } else {
             const int its = ++sctl[2];
             const int tot = ++sctl[3];
-            if (its > 100 || tot > 60 * n) {
+            if (its > 100 || tot > 60 * n || (sweep_cap > 0 && tot > sweep_cap)) {
               sctl[5] = 1;
               sctl[1] = -1;
               sctl[4] = kActStop;
@@ -1230,7 +1230,8 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
 #undef ZZ
 }
 
-__global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, double* ws, int32_t* status) {
+__global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, double* ws, int32_t* status,
+                                                          int sweep_cap) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
   __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1) + 3 * 64];
@@ -1241,9 +1242,9 @@ __global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, doub
   __shared__ ZOp zops[2];
   double* base = ws + it.ws;
   if (it.n <= kLdsMaxn)
-    eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops);
+    eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
   else
-    eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops);
+    eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
 }
 
 // U = Q U' for the reflectors of the Hessenberg reduction, Q = H_0 H_1 ... H_{n-3} with

@@ -55,16 +55,50 @@ __global__ __launch_bounds__(256) void k_synth(const SynthTask* tasks, const Lay
 }
 
 // I_out[i][k][r] = mu_q sum_p F_r[i][q][k][r][p] I0[p] (eq. 1 with E = mu_q I0).
-__global__ void k_radiance(const Layer* layers, int layer, int q, const double* quad, const double* F,
+__global__ void k_radiance(const Layer* layers, int layer, int q, int kshift, const double* quad, const double* F,
                            double i0, double i1, double i2, double i3, double* I_out) {
   const Layer ly = layers[layer];
   const int N = ly.N, nphi = ly.n_dphi;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N * nphi * 4) return;
   const int i = t / (nphi * 4), k = (t / 4) % nphi, r = t % 4;
-  const double* f = F + ly.out_off + (((int64_t)i * N + q) * nphi + k) * 16 + r * 4;
+  const int kd = (k - kshift + nphi) % nphi;  // phi_k - phi0 on the grid
+  const double* f = F + ly.out_off + (((int64_t)i * N + q) * nphi + kd) * 16 + r * 4;
   const double muq = quad[ly.quad_off + q];
   I_out[t] = muq * (f[0] * i0 + f[1] * i1 + f[2] * i2 + f[3] * i3);
+}
+
+// I(-mu_i, phi_k) = mu_q F_r(i <- q, phi_k - phi0) I0 with F_r summed from the per-order responses
+// (eq. 12 with eq. 1 and 39): I_r = 1/2 sum_m c_m sum_p tau_rp(m (phi_k - phi0)) R^m[(i,r),(q,p)] I0_p.
+__global__ void k_radiance_series(const Layer* layers, const Item* items, int layer, int q, double phi0,
+                                  const double* ws, double i0, double i1, double i2, double i3, double* I_out) {
+  const Layer ly = layers[layer];
+  const int N = ly.N, nphi = ly.n_dphi, n = 4 * N;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * nphi * 4) return;
+  const int i = t / (nphi * 4), k = (t / 4) % nphi, r = t % 4;
+  const double d = 6.283185307179586 * k / nphi - phi0;
+  const double in[4] = {i0, i1, i2, i3};
+  const bool row_iq = r < 2;
+  double acc = 0.0;
+  for (int m = 0; m < ly.M; ++m) {
+    const Item it = items[ly.item0 + m];
+    const double* R = ws + it.ws + (int64_t)kBufE * n * n + (int64_t)(4 * i + r) * n + 4 * q;
+    double sn, cs;
+    sincos(m * d, &sn, &cs);
+    double same = 0.0, mixed = 0.0;
+    for (int p = 0; p < 4; ++p) {
+      const double v = R[p] * in[p];
+      if ((p < 2) == row_iq)
+        same += v;
+      else
+        mixed += v;
+    }
+    // mixed blocks: +sin on UV <- IQ, -sin on IQ <- UV
+    const double term = cs * same + (row_iq ? -sn : sn) * mixed;
+    acc += (m == 0 ? 1.0 : 2.0) * term;
+  }
+  I_out[t] = 0.5 * acc;
 }
 
 }  // namespace vbrdf

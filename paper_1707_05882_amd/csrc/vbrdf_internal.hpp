@@ -72,7 +72,8 @@ __global__ void k_assemble(const Item* items, const Layer* layers, const double*
 // C = op(A) B, written transposed (C[c][r]) when transC is set
 __global__ void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB, int bufC, int transC,
                        const int32_t* status);
-__global__ void k_eigen(const Item* items, double* ws, int32_t* status);
+// sweep_cap: largest number of QR sweeps per problem (above it the layer is NUMERIC), 0 = default
+__global__ void k_eigen(const Item* items, double* ws, int32_t* status, int sweep_cap);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
@@ -121,8 +122,9 @@ __host__ __device__ inline void xcd_split(int id, int tiles, int& group, int& ti
   tile = rem / kXcds;
   group = blk * kXcds + rem % kXcds;
 }
+// R^m into kBufE; with transmission also T^m = (U S'^-1 - U T'^-1) R0 into kBufF
 __global__ void k_response(const Item* items, const Layer* layers, const double* quad, double* ws,
-                           const int32_t* status);
+                           const int32_t* status, int transmission);
 __global__ void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
                         const double* ws, double* F, const int32_t* status);
 // Device tables and launch shape of a solve: the plan's, or those of the allocation-free entry
@@ -137,6 +139,9 @@ struct LaunchSet {
   int max_n = 0, max_N = 0;
   int trsm_tiles = 0;   // row tiles of the right division (largest item)
   size_t trsm_lds = 0;  // its LDS bytes
+  int qr_sweep_cap = 0;       // 0 = the eigensolver's default
+  bool transmission = false;  // also write the per-order transmission T^m
+  int precision = 0;          // VBRDF_PRECISION_*
 };
 
 // Records the calling thread's error message (returned by vbrdf_last_error) and returns code.
@@ -147,7 +152,12 @@ constexpr int kNumSolveStages = 16;
 void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef, double* F_r,
                    int32_t* layer_status, hipStream_t s, hipEvent_t* evs);
 
-__global__ void k_radiance(const Layer* layers, int layer, int q, const double* quad, const double* F,
+// Radiance of eq. 1 from the F_r table, the incident azimuth being kshift grid steps
+__global__ void k_radiance(const Layer* layers, int layer, int q, int kshift, const double* quad, const double* F,
                            double i0, double i1, double i2, double i3, double* I_out);
+// The same at an arbitrary incident azimuth phi0, summing the Fourier series over the layer's
+// per-order responses R^m kept in the workspace
+__global__ void k_radiance_series(const Layer* layers, const Item* items, int layer, int q, double phi0,
+                                  const double* ws, double i0, double i1, double i2, double i3, double* I_out);
 
 }  // namespace vbrdf

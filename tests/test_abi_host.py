@@ -1,6 +1,7 @@
 """Host-side checks of the C-ABI library (no GPU needed): loading, exported symbols, host-only
 entry points and argument validation that fails before any device call."""
 
+import ctypes
 import os
 import re
 
@@ -29,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert binding.abi_version() == binding.ABI_VERSION == 1
+    assert binding.abi_version() == binding.ABI_VERSION == 2
 
 
 @pytest.mark.parametrize("N", [1, 2, 3, 8, 32, 64, 128])
@@ -57,8 +58,13 @@ def test_gauss_nodes_rejects_bad_order():
     (dict(N=[129], L=[4], M=[2], n_dphi=[8]), binding.E_UNSUPPORTED),  # N above the maximum
     (dict(N=[8], L=[600], M=[600], n_dphi=[8]), binding.E_UNSUPPORTED),  # M above the maximum
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], precision=7), binding.E_UNSUPPORTED),
-    (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=4), binding.E_UNSUPPORTED),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=64), binding.E_UNSUPPORTED),  # unknown flag
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=3), binding.E_UNSUPPORTED),  # timing + graph
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=16), binding.E_INVALID),  # FP64 fallback flag on FP64
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], qr_sweep_cap=-1), binding.E_INVALID),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace=0x1000 + 8, workspace_bytes=1 << 30), binding.E_INVALID),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace_bytes=4096), binding.E_INVALID),  # bytes, no pointer
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace=0x100000, workspace_bytes=256), binding.E_NOMEM),
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace_cap_bytes=1024), binding.E_NOMEM),
 ])
 def test_plan_validation(kw, code):
@@ -75,3 +81,39 @@ def test_null_plan_calls_are_rejected():
     assert lib.vbrdf_plan_output_bytes(None) == 0
     assert lib.vbrdf_stage_name(0).decode() == "validate"
     assert lib.vbrdf_stage_name(99) is None
+
+
+def test_workspace_query_matches_the_item_blocks():
+    """Eight n x n matrices, ten n-vectors and the Legendre table per (layer, order), 256-byte
+    aligned: the figure a caller-owned workspace must reach."""
+    N, L, M = [8, 5], [6, 9], [4, 9]
+    got = binding.workspace_query(N, L, M, [3, 4])
+    want = 0
+    for n_, l_, m_ in zip(N, L, M):
+        n = 4 * n_
+        blk = 8 * n * n + 10 * n + l_ * n_ * 3
+        want += m_ * ((blk + 31) // 32 * 32) * 8
+    assert got == want
+    with pytest.raises(binding.VbrdfError) as e:
+        binding.workspace_query([8], [4], [5], [8])
+    assert e.value.code == binding.E_INVALID
+
+
+def test_noalloc_argument_checks_before_any_device_call():
+    lib = binding.load()
+    fake = 0x100000
+    args = lambda N, L, M, P: (N, L, M, P, fake, fake, fake, fake, fake, None)
+    assert lib.vbrdf_solve_noalloc(8, 4, 2, 8, None, fake, fake, fake, fake, None) == binding.E_INVALID
+    assert lib.vbrdf_solve_noalloc(*args(0, 4, 2, 8)) == binding.E_INVALID
+    assert lib.vbrdf_solve_noalloc(*args(8, 4, 5, 8)) == binding.E_INVALID
+    assert lib.vbrdf_solve_noalloc(*args(129, 4, 2, 8)) == binding.E_UNSUPPORTED
+    assert lib.vbrdf_solve_noalloc(*args(128, 256, 256, 8)) == binding.E_NOMEM
+    assert "scratch" in binding.last_error()
+
+
+def test_radiance_and_inspect_reject_a_null_plan():
+    lib = binding.load()
+    i0 = (ctypes.c_double * 4)(1.0, 0.0, 0.0, 0.0)
+    assert lib.vbrdf_radiance(None, None, 0, 0, 0.0, i0, None, None) == binding.E_INVALID
+    assert lib.vbrdf_plan_inspect(None, 0, 0, None, None, None, None, None) == binding.E_INVALID
+    assert lib.vbrdf_plan_stage_times(None, None, 0) == binding.E_INVALID

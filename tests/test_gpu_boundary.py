@@ -1,0 +1,130 @@
+"""GPU checks of the boundary's optional outputs and controls, through the C-ABI: transmission,
+flux conservation, radiance at an arbitrary incident azimuth, the forced NUMERIC status, a
+caller-owned workspace and the Python entry point."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dom
+from oracle.quadrature import double_gauss
+from paper_1707_05882_amd import api, binding
+from paper_1707_05882_amd.api import BRDFSolver
+from workloads.layers import hg_like_coefficients
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU tests need a ROCm device")
+    binding.load()
+
+
+def hg(seed, L):
+    return hg_like_coefficients(np.random.default_rng(seed), L)[0]
+
+
+def test_transmission_matches_oracle_every_order():
+    """T^m (downward field at the base, incident stream included) against the oracle's full 8N
+    solve for the same unit stream inputs (Sec. 3.C, eq. 49-56)."""
+    N, L, tau, om = 11, 16, 2.5, 0.95
+    coef = hg(81, L)
+    s = BRDFSolver([N], [L], [L], [6], flags=binding.FLAG_EMIT_TRANSMISSION)
+    s([tau], [om], [coef])
+    mu, al = double_gauss(N)
+    for m in range(L):
+        Ro, To = dom.solve_order(coef, om, tau, m, mu, al, want_transmission=True)
+        R, _, T = s.plan.inspect(0, m, transmission=True)
+        scale = np.abs(To).max()
+        assert np.abs(R - Ro).max() < 1e-9 * np.abs(Ro).max() + 1e-12 * scale, m
+        assert np.abs(T - To).max() < 1e-9 * scale, m
+
+
+@pytest.mark.parametrize("N,L,tau", [(6, 12, 0.5), (16, 32, 8.0)])
+def test_flux_conservation_at_unit_albedo(N, L, tau):
+    """Pin P10 on the GPU: with omega = 1 (clamped to 1 - 1e-12) and L <= 2N, the reflected plus
+    transmitted m = 0 flux of every unit I stream equals the incident flux:
+    (pi / mu_q) sum_i alpha_i mu_i (R^0 + T^0)[(i, I), (q, I)] = 1."""
+    coef = hg(82 + N, L)
+    s = BRDFSolver([N], [L], [1], [1], flags=binding.FLAG_EMIT_TRANSMISSION)
+    s([tau], [1.0], [coef])
+    R, _, T = s.plan.inspect(0, 0, transmission=True)
+    mu, al = double_gauss(N)
+    for q in range(N):
+        flux = np.pi / mu[q] * np.sum(al * mu * (R[0::4, 4 * q] + T[0::4, 4 * q]))
+        assert abs(flux - 1.0) < 1e-9, (q, flux)
+
+
+def test_radiance_at_arbitrary_incident_azimuth():
+    """eq. 1 with the beam at azimuth phi0: on the grid it reads the table shifted by phi0's grid
+    steps; off the grid it sums the Fourier series (eq. 12) at phi_k - phi0, checked against the
+    oracle's per-order responses summed at the same angles."""
+    N, L, P, tau, om = 7, 10, 9, 1.5, 0.9
+    coef = hg(83, L)
+    s = BRDFSolver([N], [L], [L], [P])
+    F = s([tau], [om], [coef])[0].cpu().numpy()
+    mu, al = double_gauss(N)
+    q, I0 = 3, np.array([1.0, 0.4, -0.3, 0.2])
+    out = torch.empty(N * P * 4, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    j = 4
+    s.plan.radiance(s.F, 0, q, I0, out, stream, phi0=2 * np.pi * j / P)
+    torch.cuda.synchronize()
+    ref = mu[q] * np.einsum("ikrp,p->ikr", np.roll(F[:, q], j, axis=1), I0)
+    assert np.abs(out.cpu().numpy().reshape(N, P, 4) - ref).max() < 1e-14 * np.abs(ref).max()
+    phi0 = 0.3717
+    s.plan.radiance(s.F, 0, q, I0, out, stream, phi0=phi0)
+    torch.cuda.synchronize()
+    Ro = [dom.solve_order(coef, om, tau, m, mu, al) for m in range(L)]
+    d = 2 * np.pi * np.arange(P) / P - phi0
+    Fq = np.zeros((N, P, 4, 4))
+    for m, R in enumerate(Ro):
+        Rb = R.reshape(N, 4, N, 4)[:, :, q, :]  # (i, r, p)
+        Fq += (1.0 if m == 0 else 2.0) * dom.azimuth_factors(m, d)[None] * Rb[:, None]
+    ref = 0.5 * np.einsum("ikrp,p->ikr", Fq, I0)
+    assert np.abs(out.cpu().numpy().reshape(N, P, 4) - ref).max() < TOL * np.abs(ref).max()
+
+
+def test_sweep_cap_forces_numeric_status():
+    """A plan whose QR sweep cap is too small for the problem reports NUMERIC for the layer and
+    NaN-fills its F_r, with every kernel exiting normally."""
+    coef = hg(84, 8)
+    s = BRDFSolver([8], [8], [8], [4], qr_sweep_cap=1)
+    t, w, c = s.upload([1.0], [0.9], [coef])
+    s.solve_device(t, w, c)
+    torch.cuda.synchronize()
+    assert s.status.cpu().tolist() == [binding.E_NUMERIC]
+    assert torch.isnan(s.layer(0)).all()
+    with pytest.raises(binding.VbrdfError):
+        s.check()
+
+
+def test_caller_workspace_is_used():
+    """A plan that borrows a caller-owned workspace of vbrdf_workspace_query bytes gives the same
+    result, bit for bit, as one that owns its workspace."""
+    N, L, M, P = [9, 5], [12, 6], [12, 6], [4, 3]
+    layers = [(2.0, 0.97, hg(85, 12)), (0.4, 0.6, hg(86, 6))]
+    need = binding.workspace_query(N, L, M, P)
+    ws = torch.empty(need // 8 + 64, dtype=torch.float64, device="cuda")
+    assert ws.data_ptr() % 256 == 0
+    own = BRDFSolver(N, L, M, P)
+    Fo = [f.clone() for f in own([l[0] for l in layers], [l[1] for l in layers], [l[2] for l in layers])]
+    bor = BRDFSolver(N, L, M, P, workspace=ws, workspace_bytes=ws.numel() * 8)
+    assert bor.plan.workspace_bytes() == need
+    Fb = bor([l[0] for l in layers], [l[1] for l in layers], [l[2] for l in layers])
+    for a, b in zip(Fo, Fb):
+        assert torch.equal(a, b)
+
+
+def test_python_brdf_entry_point():
+    coef = hg(87, 9)
+    F = api.brdf(1.2, 0.93, coef, 6, 9, 5)
+    Fo = dom.brdf(coef, 1.2, 0.93, 6, 9, 5)
+    assert tuple(F.shape) == (6, 6, 5, 4, 4)
+    assert np.abs(F.cpu().numpy() - Fo).max() < TOL * np.abs(Fo[..., 0, 0]).max()
+    Fs = api.brdf([1.2, 3.0], [0.93, 0.8], [coef, hg(88, 5)], [6, 4], [9, 5], [5, 3])
+    assert len(Fs) == 2 and torch.equal(Fs[0], F)
