@@ -196,6 +196,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batched")
     ap.add_argument("--graph-steps", type=int, default=5, help="replays of the hipGraph timed beside the headline")
+    ap.add_argument("--precision", choices=["fp64", "fp32_refined"], default="fp64",
+                    help="arithmetic of the boundary solves of the timed path")
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="solves of the other precision timed for the comparison block (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates HBM byte counters)")
@@ -227,8 +231,10 @@ def main():
     dev = torch.device("cuda:0")
     layers = workload(args.workload)
     units = layers.units()
+    prec_code = {"fp64": binding.PRECISION_FP64, "fp32_refined": binding.PRECISION_FP32_REFINED}
     t_plan = time.perf_counter()
-    plan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, flags=binding.FLAG_STAGE_TIMING)
+    plan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, precision=prec_code[args.precision],
+                        flags=binding.FLAG_STAGE_TIMING)
     plan_ms = (time.perf_counter() - t_plan) * 1e3
     tau = torch.as_tensor(layers.tau, device=dev)
     omega = torch.as_tensor(layers.omega, device=dev)
@@ -269,7 +275,8 @@ def main():
     graph_ms = None
     gsteps = max(1, min(args.graph_steps, args.steps))
     try:
-        gplan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, flags=binding.FLAG_GRAPH)
+        gplan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, precision=prec_code[args.precision],
+                             flags=binding.FLAG_GRAPH)
         gstream = torch.cuda.Stream()
         Fg = torch.empty_like(F)
         with torch.cuda.stream(gstream):
@@ -287,6 +294,29 @@ def main():
         gplan.close()
     except binding.VbrdfError as e:
         print(f"graph replay unavailable: {e}", file=sys.stderr)
+
+    # the other precision on the same inputs: a few timed solves and its error against the oracle
+    compare = None
+    if args.compare_steps > 0:
+        other = "fp32_refined" if args.precision == "fp64" else "fp64"
+        cplan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, precision=prec_code[other])
+        Fc = torch.empty_like(F)
+        sc = torch.empty_like(status)
+        cplan.solve(tau, omega, coef, Fc, sc, stream.cuda_stream)
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(args.compare_steps):
+            cplan.solve(tau, omega, coef, Fc, sc, stream.cuda_stream)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        cms = c0.elapsed_time(c1) / args.compare_steps
+        cerr, _ = err_vs_oracle(Fc, layers, layers.name)
+        compare = {"precision": other, "ms_per_step": cms, "value": units / (cms / 1e3),
+                   "err_vs_oracle": cerr, "status_ok": bool((sc.cpu().numpy() == 0).all()),
+                   "speedup_of_headline": cms / ms}
+        cplan.close()
+        del Fc
 
     dom_stage = max(stages, key=stages.get)
     bound, work, unit = stage_work(dom_stage, layers)
@@ -311,19 +341,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": layers.name, "layers": layers.n_layers,
                    "N": layers.N[0] if one else sorted(set(layers.N)),
                    "L": layers.L[0] if one else "2N", "M": layers.M[0] if one else "2N",
                    "n_dphi": layers.n_dphi[0] if one else "2N", "units_per_step": units,
-                   "precision": "fp64", "base": "black"},
+                   "precision": args.precision, "base": "black"},
         "err_vs_oracle": err,
         "err_layers_checked": n_checked,
         "physical_rhs_per_s": sum(m * 4 * n for m, n in zip(layers.M, layers.N)) / (ms / 1e3),
         "plan_ms": plan_ms,
         "roofline": roofline,
         "graph_ms_per_step": graph_ms,
+        "compare": compare,
     }
     if not args.no_cpu_baseline:
         print("timing the CPU oracle sample", file=sys.stderr, flush=True)

@@ -94,7 +94,10 @@ typedef struct vbrdf_plan_desc {
   /* Largest number of QR sweeps per eigenproblem before the layer is reported NUMERIC; 0 = the
    * default of 60 sweeps per row. A small cap forces the NUMERIC status (for tests). */
   int32_t qr_sweep_cap;
-  int32_t reserved;          /* must be 0 */
+  /* FP32_REFINED: correction steps of the boundary solve after the first FP32 solve; 0 = the
+   * default (2), -1 = none (the unrefined FP32 solve then fails the convergence test: for tests of
+   * the fallback and of NONCONVERGED). Must be 0 for FP64. */
+  int32_t refine_steps;
 } vbrdf_plan_desc;
 
 /* ABI version of the loaded library (VBRDF_ABI_VERSION). */

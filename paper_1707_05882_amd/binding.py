@@ -62,7 +62,7 @@ class PlanDesc(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_uint64),
         ("qr_sweep_cap", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("refine_steps", ctypes.c_int32),
     ]
 
 
@@ -158,7 +158,7 @@ class _Desc:
     """Keeps a PlanDesc and the shape arrays it points to alive together."""
 
     def __init__(self, N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes,
-                 qr_sweep_cap):
+                 qr_sweep_cap, refine_steps=0):
         self.N, self.L, self.M, self.n_dphi = (_as_list(v) for v in (N, L, M, n_dphi))
         nl = len(self.N)
         if not (len(self.L) == len(self.M) == len(self.n_dphi) == nl):
@@ -167,7 +167,7 @@ class _Desc:
         self.keep = [arr(self.N), arr(self.L), arr(self.M), arr(self.n_dphi)]
         ws = _ptr(workspace) if workspace is not None else None
         self.desc = PlanDesc(ABI_VERSION, nl, *self.keep, int(precision), int(flags), int(workspace_cap_bytes),
-                             ws, int(workspace_bytes), int(qr_sweep_cap), 0)
+                             ws, int(workspace_bytes), int(qr_sweep_cap), int(refine_steps))
         self.n_layers = nl
 
 
@@ -183,8 +183,9 @@ class Plan:
     """Owns a vbrdf_plan. Shapes are per-layer lists (or scalars for one layer)."""
 
     def __init__(self, N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, workspace_cap_bytes=0,
-                 workspace=None, workspace_bytes=0, qr_sweep_cap=0):
-        d = _Desc(N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes, qr_sweep_cap)
+                 workspace=None, workspace_bytes=0, qr_sweep_cap=0, refine_steps=0):
+        d = _Desc(N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes, qr_sweep_cap,
+                  refine_steps)
         self.N, self.L, self.M, self.n_dphi = d.N, d.L, d.M, d.n_dphi
         self.flags = int(flags)
         self.precision = int(precision)

@@ -172,7 +172,10 @@ static vbrdf_status check_desc(const vbrdf_plan_desc* d) {
   if ((d->flags & VBRDF_FLAG_DISABLE_FP64_FALLBACK) && d->precision != VBRDF_PRECISION_FP32_REFINED)
     return fail(VBRDF_E_INVALID, "DISABLE_FP64_FALLBACK needs the FP32_REFINED precision");
   if (d->qr_sweep_cap < 0) return fail(VBRDF_E_INVALID, "qr_sweep_cap must be >= 0 (got %d)", d->qr_sweep_cap);
-  if (d->reserved != 0) return fail(VBRDF_E_INVALID, "reserved descriptor field must be 0");
+  if (d->refine_steps < -1 || d->refine_steps > 8)
+    return fail(VBRDF_E_INVALID, "refine_steps must lie in [-1, 8] (got %d)", d->refine_steps);
+  if (d->refine_steps != 0 && d->precision != VBRDF_PRECISION_FP32_REFINED)
+    return fail(VBRDF_E_INVALID, "refine_steps needs the FP32_REFINED precision");
   if (d->workspace_bytes && !d->workspace) return fail(VBRDF_E_INVALID, "workspace_bytes given without a workspace");
   if (d->workspace && (reinterpret_cast<uintptr_t>(d->workspace) & 255))
     return fail(VBRDF_E_INVALID, "caller workspace must be 256-byte aligned");
@@ -286,6 +289,8 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
   p->precision = d->precision;
   p->transmission = (d->flags & VBRDF_FLAG_EMIT_TRANSMISSION) != 0;
   p->qr_sweep_cap = d->qr_sweep_cap;
+  p->no_fallback = (d->flags & VBRDF_FLAG_DISABLE_FP64_FALLBACK) != 0;
+  p->refine_steps = d->refine_steps == 0 ? kBoundaryRefineSteps : (d->refine_steps < 0 ? 0 : d->refine_steps);
   if (d->flags & VBRDF_FLAG_STAGE_TIMING) {
     p->timing = true;
     p->ev.assign((size_t)kTimedSolves * (kNumStages + 1), nullptr);
@@ -389,12 +394,36 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   mark();
   k_bcbuild<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, LuBufs{{kBufZ, kBufX}, {kBufG, kBufF}});
-  mark();
-  k_trsm<<<xcd_grid(2 * ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(
-      p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status,
-      TrsmBufs{{kBufG, kBufF}, {kBufU, kBufU}, {kBufYS, kBufYT}, 2});  // U S'^-1, U T'^-1
-  mark();
+  const LuBufs lub{{kBufZ, kBufX}, {kBufG, kBufF}, 0};
+  const TrsmBufs trb{{kBufG, kBufF}, {kBufU, kBufU}, {kBufYS, kBufYT}, 2, 0};  // U S'^-1, U T'^-1
+  const dim3 xg(xcd_grid(2 * ni, p->trsm_tiles));
+  if (p->precision == VBRDF_PRECISION_FP32_REFINED) {
+    // FP32 factorisations and right divisions, refined against FP64 residuals; sides that do not
+    // converge are redone in FP64 (or reported NONCONVERGED when the fallback is disabled)
+    const size_t lds32 = sizeof(float) * (size_t)mn * (kTrsmRows + 1 + 2);
+    const dim3 rg(gt, gt, 2 * ni);
+    k_lu32<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status);
+    mark();
+    k_trsm32<<<xg, 64, lds32, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, 0);
+    for (int r = 0; r < p->refine_steps; ++r) {
+      k_resid<<<rg, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+      k_trsm32<<<xg, 64, lds32, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, 1);
+    }
+    k_resid<<<rg, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+    k_bcheck<<<ni, 64, 0, s>>>(p->items_d, p->ws_d, layer_status, p->no_fallback ? 1 : 0);
+    LuBufs lf = lub;
+    lf.only_flagged = 1;
+    TrsmBufs tf = trb;
+    tf.only_flagged = 1;
+    k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, lf);
+    k_trsm<<<xg, 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, tf);
+    mark();
+  } else {
+    k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, lub);
+    mark();
+    k_trsm<<<xg, 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, trb);
+    mark();
+  }
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status,
                                                        p->transmission ? 1 : 0);
   mark();

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/vbrdf.h"
+
 namespace vbrdf {
 
 constexpr int kMaxN = 128;          // nodes per hemisphere
@@ -85,11 +87,34 @@ __global__ void k_hqapply(const Item* items, int n_items, int tiles, double* ws,
 // slots of the extras block.
 struct LuBufs {
   int32_t src[2], dst[2];
+  int32_t only_flagged;  // factor only the sides whose FP32 refinement asked for the FP64 solve
 };
 struct TrsmBufs {
   int32_t a[2], rhs[2], y[2];
-  int32_t sides;  // 1 or 2 matrices per item
+  int32_t sides;         // 1 or 2 matrices per item
+  int32_t only_flagged;  // as in LuBufs
 };
+
+// State of the FP32-refined boundary solve per item, in the extras block at [3n, 3n + 4) (free
+// at that stage): the largest residual entry of each side and of U (non-negative doubles compared
+// through their bit patterns by atomicMax), and per side whether the FP64 solve must be redone.
+struct BoundaryFlags {
+  unsigned long long resmax[2];
+  unsigned long long umax;
+  int32_t fallback[2];
+};
+__host__ __device__ inline BoundaryFlags* boundary_flags(double* ex, int n) {
+  return reinterpret_cast<BoundaryFlags*>(ex + 3 * (int64_t)n);
+}
+// Refined-path kernels: FP32 LU of S' and T' (factors as floats in the first half of the k_lu
+// output buffers), FP32 right division (set or accumulate), FP64 residual U - Y A rounded to FP32
+// into kBufE, and the end-of-refinement check (fallback flag, or NONCONVERGED when the FP64
+// fallback is disabled).
+constexpr int kLu32LdsMaxn = 192;  // largest n factored in LDS in FP32
+__global__ void k_lu32(const Item* items, double* ws, int32_t* status);
+__global__ void k_trsm32(const Item* items, int n_items, int tiles, double* ws, int32_t* status, int accumulate);
+__global__ void k_resid(const Item* items, double* ws, const int32_t* status);
+__global__ void k_bcheck(const Item* items, double* ws, int32_t* status, int no_fallback);
 __global__ void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b);
 __global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status, TrsmBufs b);
 // Eigenpair refinement of the homogeneous step (between the eigenvector back-transformation and the
@@ -142,7 +167,10 @@ struct LaunchSet {
   int qr_sweep_cap = 0;       // 0 = the eigensolver's default
   bool transmission = false;  // also write the per-order transmission T^m
   int precision = 0;          // VBRDF_PRECISION_*
+  bool no_fallback = false;   // FP32-refined: NONCONVERGED instead of the FP64 redo
+  int refine_steps = 0;       // FP32-refined: correction steps of the boundary solve
 };
+constexpr int kBoundaryRefineSteps = 2;  // FP32-refined boundary solve: correction steps
 
 // Records the calling thread's error message (returned by vbrdf_last_error) and returns code.
 int32_t vbrdf_fail(int32_t code, const char* fmt, ...);

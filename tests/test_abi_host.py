@@ -62,6 +62,8 @@ def test_gauss_nodes_rejects_bad_order():
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=3), binding.E_UNSUPPORTED),  # timing + graph
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], flags=16), binding.E_INVALID),  # FP64 fallback flag on FP64
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], qr_sweep_cap=-1), binding.E_INVALID),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], refine_steps=1), binding.E_INVALID),  # refine steps on FP64
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], precision=1, refine_steps=-2), binding.E_INVALID),
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace=0x1000 + 8, workspace_bytes=1 << 30), binding.E_INVALID),
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace_bytes=4096), binding.E_INVALID),  # bytes, no pointer
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace=0x100000, workspace_bytes=256), binding.E_NOMEM),
