@@ -67,6 +67,9 @@ typedef int32_t vbrdf_status;
 /* Keep the per-order diffuse-plus-direct transmission at the base (the downward field at tau0 for
  * the same unit stream inputs, direct stream included) for vbrdf_plan_inspect. */
 #define VBRDF_FLAG_EMIT_TRANSMISSION 4
+/* Keep what the adjoint needs (copies of E~ and F~ per order, the layer status) so that
+ * vbrdf_backward can follow vbrdf_solve; adds 8 (4N)^2 doubles of workspace per order. */
+#define VBRDF_FLAG_SAVE_FOR_BACKWARD 8
 /* FP32_REFINED only: report VBRDF_E_NONCONVERGED for a layer whose refinement stalls instead of
  * redoing its boundary solve in FP64. */
 #define VBRDF_FLAG_DISABLE_FP64_FALLBACK 16
@@ -173,6 +176,23 @@ int32_t vbrdf_plan_stage_times(vbrdf_plan* plan, float* ms_out, int32_t cap);
 
 /* Name of stage i (static string), or NULL when out of range. */
 const char* vbrdf_stage_name(int32_t i);
+
+/* Gradients of a scalar loss with respect to the layer parameters, given its gradient dF_r with
+ * respect to F_r (same layout as F_r): reverse mode through the synthesis (eq. 12, 39), the
+ * boundary solve (eq. 49-56), the matrix functions of the eigen-decomposition (eq. 43-45, by the
+ * Daleckii-Krein form of their derivative) and the assembly (eq. 41-42, 9). The plan must have
+ * been created with VBRDF_FLAG_SAVE_FOR_BACKWARD, and the last vbrdf_solve on it must have had the
+ * same tau, omega and coef (its per-order state is reused; it must not be overwritten by another
+ * solve before this call's work has run). Device pointers, enqueued on `stream`:
+ *   tau, omega, coef        the forward's inputs
+ *   dF_r                    dLoss / dF_r, doubles in the F_r layout
+ *   dtau[n_layers], domega[n_layers], dcoef (layout of coef)   outputs, overwritten (not added to)
+ * A layer whose forward failed gets NaN gradients. d/d omega is taken at the clamped albedo
+ * (omega <= 1 - 1e-12); d/d alpha1_0 is reported although alpha1_0 is fixed at 1 by the
+ * normalisation. Errors: INVALID (null pointer, plan without the flag, no forward solve yet),
+ * DEVICE. */
+vbrdf_status vbrdf_backward(vbrdf_plan* plan, const double* tau, const double* omega, const double* coef,
+                            const double* dF_r, double* dtau, double* domega, double* dcoef, void* stream);
 
 /* Stokes radiances of eq. 1: for a beam of Stokes vector I0 (host array of 4) incident on node q
  * at azimuth phi0 (radians), I_out[i][k][r] = mu_q sum_p F_r(i <- q, phi_k - phi0)[r][p] I0[p],

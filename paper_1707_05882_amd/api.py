@@ -65,6 +65,63 @@ class BRDFSolver:
         return self._views[i]
 
 
+class VbrdfFunction(torch.autograd.Function):
+    """F_r (flat, all layers packed) as a differentiable function of tau, omega and the packed
+    coefficients; the backward pass is the library's adjoint (vbrdf_backward).
+
+    F = VbrdfFunction.apply(tau, omega, coef, solver)   # solver: BRDFSolver with save_for_backward
+    """
+
+    @staticmethod
+    def forward(ctx, tau, omega, coef, solver):
+        tau, omega, coef = (x.detach().contiguous() for x in (tau, omega, coef))
+        solver.solve_device(tau, omega, coef)
+        torch.cuda.synchronize(solver.device)
+        solver.check()
+        solver.version += 1
+        ctx.version = solver.version
+        ctx.solver = solver
+        ctx.save_for_backward(tau, omega, coef)
+        return solver.F.clone()
+
+    @staticmethod
+    def backward(ctx, gF):
+        tau, omega, coef = ctx.saved_tensors
+        solver = ctx.solver
+        if solver.version != ctx.version:  # another forward ran since: recompute this one's state
+            solver.solve_device(tau, omega, coef)
+            solver.version += 1
+            ctx.version = solver.version
+        dtau, domega, dcoef = torch.empty_like(tau), torch.empty_like(omega), torch.empty_like(coef)
+        s = torch.cuda.current_stream(solver.device)
+        solver.plan.backward(tau, omega, coef, gF.contiguous(), dtau, domega, dcoef, s.cuda_stream)
+        return dtau, domega, dcoef, None
+
+
+class DifferentiableBRDF:
+    """Layers of fixed shapes whose F_r is differentiable with respect to tau, omega and coef.
+
+    model = DifferentiableBRDF(N=[32] * 64, L=[64] * 64, M=[32] * 64, n_dphi=[32] * 64)
+    F = model(tau, omega, coef)   # tau, omega: (n_layers,), coef: packed (sum 6 L,) CUDA tensors
+    loss(F).backward()            # gradients in tau.grad, omega.grad, coef.grad
+    """
+
+    def __init__(self, N, L, M, n_dphi, device="cuda"):
+        self.solver = BRDFSolver(N, L, M, n_dphi, device=device, flags=binding.FLAG_SAVE_FOR_BACKWARD)
+        self.solver.version = 0
+
+    def __call__(self, tau, omega, coef):
+        return VbrdfFunction.apply(tau, omega, coef, self.solver)
+
+    def views(self, F):
+        """Per-layer (N, N, n_dphi, 4, 4) views of a flat F."""
+        out, off = [], 0
+        for n, p in zip(self.solver.plan.N, self.solver.plan.n_dphi):
+            out.append(F[off:off + n * n * p * 16].view(n, n, p, 4, 4))
+            off += n * n * p * 16
+        return out
+
+
 _PRECISIONS = {"fp64": binding.PRECISION_FP64, "fp32_refined": binding.PRECISION_FP32_REFINED}
 
 

@@ -26,6 +26,7 @@ PRECISION_FP32_REFINED = 1
 FLAG_STAGE_TIMING = 1
 FLAG_GRAPH = 2
 FLAG_EMIT_TRANSMISSION = 4
+FLAG_SAVE_FOR_BACKWARD = 8
 FLAG_DISABLE_FP64_FALLBACK = 16
 ABI_VERSION = 2
 MAX_N = 128
@@ -38,7 +39,7 @@ EXPORTED = (
     "vbrdf_abi_version", "vbrdf_last_error", "vbrdf_gauss_nodes", "vbrdf_plan_create",
     "vbrdf_workspace_query", "vbrdf_plan_destroy", "vbrdf_plan_output_bytes", "vbrdf_plan_workspace_bytes",
     "vbrdf_solve", "vbrdf_plan_inspect", "vbrdf_radiance", "vbrdf_plan_stage_times", "vbrdf_stage_name",
-    "vbrdf_solve_noalloc",
+    "vbrdf_solve_noalloc", "vbrdf_backward",
 )
 
 
@@ -106,6 +107,8 @@ def load():
     L.vbrdf_stage_name.argtypes = [i32]
     L.vbrdf_solve_noalloc.restype = i32
     L.vbrdf_solve_noalloc.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+    L.vbrdf_backward.restype = i32
+    L.vbrdf_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     if L.vbrdf_abi_version() != ABI_VERSION:
         raise OSError("libvbrdf.so ABI version mismatch")
     _lib = L
@@ -211,6 +214,12 @@ class Plan:
     def solve(self, tau, omega, coef, F_r, layer_status, stream=0):
         _check(load().vbrdf_solve(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(F_r), _ptr(layer_status),
                                   ctypes.c_void_p(int(stream))))
+
+    def backward(self, tau, omega, coef, dF, dtau, domega, dcoef, stream=0):
+        """Gradients of a loss with respect to tau, omega and coef given dLoss/dF_r (device
+        pointers; the plan needs FLAG_SAVE_FOR_BACKWARD and a preceding solve on the same inputs)."""
+        _check(load().vbrdf_backward(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(dF), _ptr(dtau),
+                                     _ptr(domega), _ptr(dcoef), ctypes.c_void_p(int(stream))))
 
     def inspect(self, layer, m, stream=0, transmission=False):
         """Host copies of R^m (4N x 4N) and the eigenvalues of FE for one (layer, order); with

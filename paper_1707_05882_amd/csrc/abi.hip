@@ -118,6 +118,7 @@ struct vbrdf_plan : LaunchSet {
   std::vector<Layer> layers_h;
   std::vector<Item> items_h;
   bool ws_owned = true;  // false when the workspace is the caller's
+  bool solved = false;   // a forward solve has been enqueued (the adjoint reads its state)
   bool timing = false;
   bool graph = false;             // capture the solve into a hipGraph and replay it
   hipGraphExec_t gexec = nullptr;  // instantiated for the pointers in gkey
@@ -134,6 +135,7 @@ struct vbrdf_plan : LaunchSet {
     if (tasks_d) (void)hipFree(const_cast<SynthTask*>(tasks_d));
     if (quad_d) (void)hipFree(const_cast<double*>(quad_d));
     if (ws_d && ws_owned) (void)hipFree(ws_d);
+    if (status_d) (void)hipFree(status_d);
   }
 };
 
@@ -165,7 +167,7 @@ static vbrdf_status check_desc(const vbrdf_plan_desc* d) {
   if (d->precision != VBRDF_PRECISION_FP64 && d->precision != VBRDF_PRECISION_FP32_REFINED)
     return fail(VBRDF_E_UNSUPPORTED, "unknown precision %d", d->precision);
   const int known = VBRDF_FLAG_STAGE_TIMING | VBRDF_FLAG_GRAPH | VBRDF_FLAG_EMIT_TRANSMISSION |
-                    VBRDF_FLAG_DISABLE_FP64_FALLBACK;
+                    VBRDF_FLAG_SAVE_FOR_BACKWARD | VBRDF_FLAG_DISABLE_FP64_FALLBACK;
   if (d->flags & ~known) return fail(VBRDF_E_UNSUPPORTED, "unknown flags 0x%x", d->flags);
   if ((d->flags & VBRDF_FLAG_STAGE_TIMING) && (d->flags & VBRDF_FLAG_GRAPH))
     return fail(VBRDF_E_UNSUPPORTED, "stage timing and graph replay cannot be combined");
@@ -191,7 +193,7 @@ static vbrdf_status check_desc(const vbrdf_plan_desc* d) {
 }
 
 // Per-item workspace blocks, 256-byte aligned.
-static int64_t block_doubles(int N, int L) { return (item_doubles(4 * N, N, L) + 31) / 32 * 32; }
+static int64_t block_doubles(int N, int L, bool save) { return block_doubles_of(4 * N, N, L, save); }
 
 vbrdf_status vbrdf_workspace_query(const vbrdf_plan_desc* d, uint64_t* bytes) {
   if (!bytes) return fail(VBRDF_E_INVALID, "null output pointer");
@@ -199,7 +201,8 @@ vbrdf_status vbrdf_workspace_query(const vbrdf_plan_desc* d, uint64_t* bytes) {
   const vbrdf_status st = check_desc(d);
   if (st != VBRDF_OK) return st;
   int64_t total = 0;
-  for (int l = 0; l < d->n_layers; ++l) total += (int64_t)d->M[l] * block_doubles(d->N[l], d->L[l]);
+  const bool save = (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0;
+  for (int l = 0; l < d->n_layers; ++l) total += (int64_t)d->M[l] * block_doubles(d->N[l], d->L[l], save);
   *bytes = (uint64_t)total * sizeof(double);
   return VBRDF_OK;
 }
@@ -239,7 +242,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       it.L = ly.L;
       it.n = n;
       it.ws = ws_off;
-      ws_off += block_doubles(ly.N, ly.L);
+      ws_off += block_doubles(ly.N, ly.L, (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0);
       p->items_h.push_back(it);
     }
     for (int i = 0; i < ly.N; ++i)
@@ -291,6 +294,20 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
   p->qr_sweep_cap = d->qr_sweep_cap;
   p->no_fallback = (d->flags & VBRDF_FLAG_DISABLE_FP64_FALLBACK) != 0;
   p->refine_steps = d->refine_steps == 0 ? kBoundaryRefineSteps : (d->refine_steps < 0 ? 0 : d->refine_steps);
+  p->save = (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0;
+  if (p->save) {
+    for (const Layer& ly : p->layers_h)
+      if (6 * (int64_t)ly.L > 16 * (int64_t)ly.N * ly.N) {
+        delete p;
+        return fail(VBRDF_E_UNSUPPORTED, "SAVE_FOR_BACKWARD needs 6 L <= (4 N)^2 per layer");
+      }
+    hipError_t es = hipMalloc(reinterpret_cast<void**>(&p->status_d), sizeof(int32_t) * p->n_layers);
+    if (es != hipSuccess) {
+      p->status_d = nullptr;
+      delete p;
+      return fail(VBRDF_E_NOMEM, "status copy allocation failed: %s", hipGetErrorString(es));
+    }
+  }
   if (d->flags & VBRDF_FLAG_STAGE_TIMING) {
     p->timing = true;
     p->ev.assign((size_t)kTimedSolves * (kNumStages + 1), nullptr);
@@ -357,14 +374,19 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   mark();
   const int at = (mN + 15) / 16;
   k_assemble<<<dim3(at, at, ni), 256, 0, s>>>(p->items_d, p->layers_d, p->quad_d, omega, coef, p->ws_d, layer_status);
+  if (p->save) {  // E~ and F~ are overwritten later in the sequence; the adjoint needs them
+    const dim3 cg((mn * mn + 255) / 256, ni);
+    k_copy_buf<<<cg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, kBufSE, layer_status);
+    k_copy_buf<<<cg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufSF, layer_status);
+  }
   mark();
   const int gt = (mn + 63) / 64;
   const dim3 gg(gt, gt, ni);
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, 0, kBufE, kBufG, 0, layer_status);  // G = F~ E~
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufE, kBufG, 0, layer_status);  // G = F~ E~
   mark();
   k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap);
   mark();
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, 1, kBufX, kBufG, 0, layer_status);  // U' = Z X
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, kBufX, kBufG, kGemmTransA, layer_status);  // U' = Z X
   mark();
   const int hqt = (mn + kHqCols - 1) / kHqCols;
   k_hqapply<<<xcd_grid(ni, hqt), 64, 0, s>>>(p->items_d, ni, hqt, p->ws_d, layer_status);  // U = Q U'
@@ -372,8 +394,8 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   // one Newton step on the eigen-decomposition with the factored product F~ (E~ U)
   const int et = (mn + 15) / 16;
   const int tt = (mn + 31) / 32;
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, 0, layer_status);  // E~ U
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, 0, kBufG, kBufZ, 1, layer_status);  // (F~ E~ U)^T
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, kBufU, kBufG, 0, layer_status);  // E~ U
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufG, kBufZ, kGemmTransC, layer_status);  // (F~ E~ U)^T
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, layer_status);  // U^T
   k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, LuBufs{{kBufX, kBufX}, {kBufYS, kBufYS}});
   k_trsm<<<xcd_grid(ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(
@@ -383,10 +405,10 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   k_refine_close<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
   k_refine_pairs<<<dim3((mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   k_refine_delta<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufU, 0, kBufX, kBufZ, 0, layer_status);  // U (I + X) Q
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, kBufZ, 0, layer_status);  // U (I + X) Q
   k_refine_commit<<<dim3((mn * mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
-  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, 0, kBufU, kBufG, 0, layer_status);  // V = E~ U
+  k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, kBufU, kBufG, 0, layer_status);  // V = E~ U
   mark();
   k_vfix<<<ni, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   mark();
@@ -428,7 +450,52 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
                                                        p->transmission ? 1 : 0);
   mark();
   k_synth<<<p->n_tasks, 256, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
+  if (p->save) k_copy_status<<<(p->n_layers + 255) / 256, 256, 0, s>>>(layer_status, p->status_d, p->n_layers);
   mark();
+}
+
+// The adjoint sequence over all items (see k_adjoint.hip for the formulas and buffer roles).
+void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omega, const double* dF, double* dtau,
+                      double* domega, double* dcoef, hipStream_t s) {
+  const LaunchSet* p = &ls;
+  const int ni = p->n_items, mn = p->max_n, mN = p->max_N;
+  const int32_t* st = p->status_d;
+  int32_t* stw = p->status_d;
+  const int gt = (mn + 63) / 64;
+  const dim3 gg(gt, gt, ni);
+  const int et = (mn + 15) / 16;
+  const int tt = (mn + 31) / 32;
+  auto gemm = [&](int a, int b, int c, int mode) { k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, a, b, c, mode, st); };
+  k_bwd_q<<<dim3((mN * mN + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->layers_d, p->quad_d, dF, p->ws_d, st);
+  // U^-T: LU of U^T, right division of the identity
+  k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, st);
+  k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, stw, LuBufs{{kBufX, kBufX}, {kBufG, kBufG}, 0});
+  k_fill_identity<<<dim3((mn * mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufF, st);
+  k_trsm<<<xcd_grid(ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, stw,
+                                                              TrsmBufs{{kBufG, kBufG}, {kBufF, kBufF}, {kBufW, kBufW}, 1, 0});
+  gemm(kBufYS, kBufE, kBufT1, kGemmTransA);                 // P_s^T Q
+  gemm(kBufT1, kBufYS, kBufT2, kGemmTransB | kGemmNegate);  // A_s-bar
+  gemm(kBufYT, kBufE, kBufT1, kGemmTransA);
+  gemm(kBufT1, kBufYT, kBufT3, kGemmTransB | kGemmNegate);  // A_t-bar
+  gemm(kBufSE, kBufT2, kBufT4, kGemmTransA);                // F_s-bar = E~^T A_s-bar
+  gemm(kBufSE, kBufT3, kBufT5, kGemmTransA);                // F_t-bar
+  gemm(kBufT2, kBufW, kBufT1, 0);                           // A_s-bar U^-T
+  gemm(kBufT3, kBufW, kBufZ, 0);                            // A_t-bar U^-T
+  k_bwd_dscale<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, st);
+  gemm(kBufT2, kBufU, kBufG, kGemmTransB);                  // E~-bar, explicit part
+  gemm(kBufU, kBufT4, kBufT1, kGemmTransA);
+  gemm(kBufT1, kBufW, kBufT4, 0);                           // X_s = U^T F_s-bar U^-T
+  gemm(kBufU, kBufT5, kBufT1, kGemmTransA);
+  gemm(kBufT1, kBufW, kBufT5, 0);                           // X_t
+  k_bwd_dk<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, tau, p->ws_d, st);
+  k_bwd_tau<<<ni, 256, 0, s>>>(p->items_d, tau, p->ws_d, st);
+  gemm(kBufW, kBufT1, kBufT2, 0);
+  gemm(kBufT2, kBufU, kBufT3, kGemmTransB);                 // G-bar = U^-T Y U^T
+  gemm(kBufT3, kBufSE, kBufT4, kGemmTransB);                // F~-bar = G-bar E~^T
+  gemm(kBufSF, kBufT3, kBufG, kGemmTransA | kGemmAccumulate);  // E~-bar += F~^T G-bar
+  k_bwd_omega<<<ni, 256, 0, s>>>(p->items_d, p->layers_d, p->quad_d, omega, p->ws_d, st);
+  k_bwd_coef<<<ni, kCoefThreads, 0, s>>>(p->items_d, p->layers_d, p->quad_d, omega, p->ws_d, st);
+  k_bwd_reduce<<<p->n_layers, 256, 0, s>>>(p->layers_d, p->items_d, p->ws_d, st, dtau, domega, dcoef);
 }
 
 }  // namespace vbrdf
@@ -464,9 +531,11 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
       for (int i = 0; i < 6; ++i) p->gkey[i] = key[i];
     }
     HIP_TRY(hipGraphLaunch(p->gexec, s));
+    p->solved = true;
     return VBRDF_OK;
   }
   const bool rec = p->timing && p->timed < kTimedSolves;
+  p->solved = true;
   enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s,
                 rec ? &p->ev[(size_t)p->timed * (kNumStages + 1)] : nullptr);
   if (rec) ++p->timed;
@@ -514,6 +583,18 @@ int32_t vbrdf_plan_stage_times(vbrdf_plan* p, float* ms_out, int32_t cap) {
 }
 
 const char* vbrdf_stage_name(int32_t i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : nullptr; }
+
+vbrdf_status vbrdf_backward(vbrdf_plan* p, const double* tau, const double* omega, const double* coef,
+                            const double* dF_r, double* dtau, double* domega, double* dcoef, void* stream) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!p->save) return fail(VBRDF_E_INVALID, "the plan was created without SAVE_FOR_BACKWARD");
+  if (!p->solved) return fail(VBRDF_E_INVALID, "no forward solve has been enqueued on this plan");
+  if (!tau || !omega || !coef || !dF_r || !dtau || !domega || !dcoef)
+    return fail(VBRDF_E_INVALID, "null device pointer");
+  enqueue_backward(*p, tau, omega, dF_r, dtau, domega, dcoef, reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return VBRDF_OK;
+}
 
 vbrdf_status vbrdf_radiance(const vbrdf_plan* p, const double* F_r, int32_t layer, int32_t q, double phi0,
                             const double I0[4], double* I_out, void* stream) {

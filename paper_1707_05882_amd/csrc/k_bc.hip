@@ -234,8 +234,8 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
   const int which = blockIdx.y;
   double* base = ws + it.ws;
   if (b.only_flagged && !boundary_flags(base + extras_off(n), n)->fallback[which]) return;
-  double* Ag = base + (int64_t)b.src[which] * n * n;
-  double* AT = base + (int64_t)b.dst[which] * n * n;
+  double* Ag = buf_ptr(ws, it, b.src[which]);
+  double* AT = buf_ptr(ws, it, b.dst[which]);
   double* ex = base + extras_off(n);
   __shared__ double smem[kLuLds];
   __shared__ int perm[2 * kMaxn];
@@ -387,9 +387,9 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
   const int n = it.n;
   double* base = ws + it.ws;
   if (b.only_flagged && !boundary_flags(base + extras_off(n), n)->fallback[side]) return;
-  const double* AT = base + (int64_t)b.a[side] * n * n;
-  const double* U = base + (int64_t)b.rhs[side] * n * n;
-  double* Y = base + (int64_t)b.y[side] * n * n;
+  const double* AT = buf_ptr(ws, it, b.a[side]);
+  const double* U = buf_ptr(ws, it, b.rhs[side]);
+  double* Y = buf_ptr(ws, it, b.y[side]);
   // the tile stride is a compile-time constant so that LDS offsets fold into the instructions
   if (trsm_ldb(n) == kTrsmLdb)
     trsm_tile<kTrsmLdb, double, double, false>(it, side, r0, ws, AT, U, Y);

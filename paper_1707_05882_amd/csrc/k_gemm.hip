@@ -19,16 +19,17 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int kGT = 64;  // output tile
 constexpr int kGK = 16;  // K step
 
-__global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB,
-                                               int bufC, int transC, const int32_t* status) {
+__global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int bufA, int bufB, int bufC, int mode,
+                                               const int32_t* status) {
+  const bool transA = mode & kGemmTransA, transB = mode & kGemmTransB, transC = mode & kGemmTransC;
   const Item it = items[blockIdx.z];
   if (status[it.layer] != 0) return;
   const int n = it.n;
   const int r0 = blockIdx.y * kGT, c0 = blockIdx.x * kGT;
   if (r0 >= n || c0 >= n) return;
-  const double* A = ws + it.ws + (int64_t)bufA * n * n;
-  const double* B = ws + it.ws + (int64_t)bufB * n * n;
-  double* C = ws + it.ws + (int64_t)bufC * n * n;
+  const double* A = buf_ptr(ws, it, bufA);
+  const double* B = buf_ptr(ws, it, bufB);
+  double* C = buf_ptr(ws, it, bufC);
 
   __shared__ double sA[kGT][kGK + 1];
   __shared__ double sB[kGK][kGT + 1];
@@ -63,8 +64,18 @@ __global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int
     }
     // B tile: 16 k x 64 cols
     for (int t = tid; t < kGK * kGT; t += 256) {
-      int c = t % kGT, k = t / kGT;
-      sB[k][c] = (k0 + k < n && c0 + c < n) ? B[(int64_t)(k0 + k) * n + c0 + c] : 0.0;
+      int c, k;
+      double v;
+      if (transB) {  // element (k, col) of op(B) lives at B[col * n + k]: k fastest
+        k = t % kGK;
+        c = t / kGK;
+        v = (k0 + k < n && c0 + c < n) ? B[(int64_t)(c0 + c) * n + k0 + k] : 0.0;
+      } else {
+        c = t % kGT;
+        k = t / kGT;
+        v = (k0 + k < n && c0 + c < n) ? B[(int64_t)(k0 + k) * n + c0 + c] : 0.0;
+      }
+      sB[k][c] = v;
     }
     __syncthreads();
 #pragma unroll
@@ -89,7 +100,11 @@ __global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int
       for (int v = 0; v < 4; ++v) {
         const int row = r0 + wr + x * 16 + lk + 4 * v;
         const int col = c0 + wc + y * 16 + li;
-        if (row < n && col < n) C[transC ? (int64_t)col * n + row : (int64_t)row * n + col] = acc[x][y][v];
+        if (row < n && col < n) {
+          const int64_t idx = transC ? (int64_t)col * n + row : (int64_t)row * n + col;
+          const double val = (mode & kGemmNegate) ? -acc[x][y][v] : acc[x][y][v];
+          C[idx] = (mode & kGemmAccumulate) ? C[idx] + val : val;
+        }
       }
 }
 

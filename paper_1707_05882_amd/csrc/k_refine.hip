@@ -37,8 +37,8 @@ __global__ __launch_bounds__(256) void k_transpose(const Item* items, double* ws
   const int n = it.n;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
   if (r0 >= n || c0 >= n) return;
-  const double* S = ws + it.ws + (int64_t)src * n * n;
-  double* D = ws + it.ws + (int64_t)dst * n * n;
+  const double* S = buf_ptr(ws, it, src);
+  double* D = buf_ptr(ws, it, dst);
   __shared__ double t[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int r = ty; r < 32; r += 8)

@@ -56,12 +56,32 @@ __host__ __device__ inline int64_t item_doubles(int n, int N, int L) {
   return leg_off(n) + (int64_t)L * N * 3;
 }
 
+// Per-item block: the kNumBuf matrices, the extras, the Legendre table, then (plans that keep
+// the state for the adjoint) kNumBwdBuf more n x n matrices. Buffer index b < kNumBuf addresses
+// the first group, kNumBuf <= b < kNumBuf + kNumBwdBuf the second.
+constexpr int kNumBwdBuf = 8;
+enum BwdBuf : int {
+  kBufSE = kNumBuf,  // E~ kept from the forward
+  kBufSF,            // F~ kept from the forward
+  kBufW,             // U^-T
+  kBufT1, kBufT2, kBufT3, kBufT4, kBufT5  // adjoint temporaries
+};
+__host__ __device__ inline int64_t bwd_off(int n, int N, int L) { return (item_doubles(n, N, L) + 31) / 32 * 32; }
+__host__ __device__ inline int64_t block_doubles_of(int n, int N, int L, bool save) {
+  return bwd_off(n, N, L) + (save ? (int64_t)kNumBwdBuf * n * n : 0);
+}
+
 struct SynthTask {
   int32_t layer, i, q, pad;
 };
 
 constexpr int kSynthMaxM = 512;     // Fourier orders per layer
 constexpr int kSynthMaxPhi = 1024;  // azimuth samples per layer
+
+__host__ __device__ inline double* buf_ptr(double* ws, const Item& it, int b) {
+  const int64_t nn = (int64_t)it.n * it.n;
+  return ws + it.ws + (b < kNumBuf ? b * nn : bwd_off(it.n, it.N, it.L) + (b - kNumBuf) * nn);
+}
 
 // ---- kernels (one translation unit each)
 __global__ void k_validate(const Layer* layers, int n_layers, const double* tau, const double* omega,
@@ -71,9 +91,10 @@ __global__ void k_legendre(const Item* items, const Layer* layers, const double*
                            const int32_t* status);
 __global__ void k_assemble(const Item* items, const Layer* layers, const double* quad, const double* omega,
                            const double* coef, double* ws, const int32_t* status);
-// C = op(A) B, written transposed (C[c][r]) when transC is set
-__global__ void k_gemm(const Item* items, double* ws, int bufA, int transA, int bufB, int bufC, int transC,
-                       const int32_t* status);
+// C = op(A) op(B) for buffers of one item; mode: OR of the bits below (C written transposed,
+// negated, or added to the existing C)
+constexpr int kGemmTransA = 1, kGemmTransB = 2, kGemmTransC = 4, kGemmNegate = 8, kGemmAccumulate = 16;
+__global__ void k_gemm(const Item* items, double* ws, int bufA, int bufB, int bufC, int mode, const int32_t* status);
 // sweep_cap: largest number of QR sweeps per problem (above it the layer is NUMERIC), 0 = default
 __global__ void k_eigen(const Item* items, double* ws, int32_t* status, int sweep_cap);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
@@ -169,6 +190,8 @@ struct LaunchSet {
   int precision = 0;          // VBRDF_PRECISION_*
   bool no_fallback = false;   // FP32-refined: NONCONVERGED instead of the FP64 redo
   int refine_steps = 0;       // FP32-refined: correction steps of the boundary solve
+  bool save = false;          // keep the state the adjoint needs (E~, F~ copies, layer status)
+  int32_t* status_d = nullptr;  // copy of the last forward's layer status (adjoint plans)
 };
 constexpr int kBoundaryRefineSteps = 2;  // FP32-refined boundary solve: correction steps
 
@@ -179,6 +202,25 @@ int32_t vbrdf_fail(int32_t code, const char* fmt, ...);
 constexpr int kNumSolveStages = 16;
 void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef, double* F_r,
                    int32_t* layer_status, hipStream_t s, hipEvent_t* evs);
+void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omega, const double* dF, double* dtau,
+                      double* domega, double* dcoef, hipStream_t s);
+
+// ---- adjoint kernels (k_adjoint.hip)
+__global__ void k_copy_buf(const Item* items, double* ws, int src, int dst, const int32_t* status);
+__global__ void k_fill_identity(const Item* items, double* ws, int dst, const int32_t* status);
+__global__ void k_copy_status(const int32_t* src, int32_t* dst, int n);
+__global__ void k_bwd_q(const Item* items, const Layer* layers, const double* quad, const double* dF, double* ws,
+                        const int32_t* status);
+__global__ void k_bwd_dscale(const Item* items, double* ws, const int32_t* status);
+__global__ void k_bwd_dk(const Item* items, const double* tau, double* ws, const int32_t* status);
+__global__ void k_bwd_tau(const Item* items, const double* tau, double* ws, const int32_t* status);
+__global__ void k_bwd_omega(const Item* items, const Layer* layers, const double* quad, const double* omega,
+                            double* ws, const int32_t* status);
+constexpr int kCoefThreads = 256;
+__global__ void k_bwd_coef(const Item* items, const Layer* layers, const double* quad, const double* omega,
+                           double* ws, const int32_t* status);
+__global__ void k_bwd_reduce(const Layer* layers, const Item* items, const double* ws, const int32_t* status,
+                             double* dtau, double* domega, double* dcoef);
 
 // Radiance of eq. 1 from the F_r table, the incident azimuth being kshift grid steps
 __global__ void k_radiance(const Layer* layers, int layer, int q, int kshift, const double* quad, const double* F,

@@ -9,6 +9,7 @@ from .layers import (  # noqa: F401
     COEF_ROWS,
     LayerSet,
     hg_like_coefficients,
+    differentiation_targets,
     positivity_ok,
     rayleigh_coefficients,
     workload,

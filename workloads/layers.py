@@ -290,3 +290,26 @@ def workload(name: str, **kw) -> LayerSet:
     """One of: rayleigh (N=8), particulate (N=32, L=M=64), batched (256 uneven layers),
     differentiation (64 layers N=32), large (N=128, L=M=256)."""
     return WORKLOADS[name](**kw)
+
+
+def differentiation_targets(layers: LayerSet, seed: int = 40, max_tries: int = 100) -> LayerSet:
+    """Target parameters for the differentiation workload: tau* = tau (1 + 0.05 xi),
+    omega* = min(omega + 0.01 xi, 0.999), coefficient* = coefficient (1 + 0.02 xi_l) for degrees
+    l >= 1 of all six families (xi ~ N(0, 1), one PCG64 substream per layer); a perturbed set that
+    fails the validity inequalities is redrawn from the same stream, with the 0.02 amplitude halved
+    after every 20 failed draws (sets close to the validity boundary)."""
+    taus, omegas, coefs = [], [], []
+    for i, rng in enumerate(_streams(seed, layers.n_layers)):
+        taus.append(layers.tau[i] * (1.0 + 0.05 * rng.standard_normal()))
+        omegas.append(min(layers.omega[i] + 0.01 * rng.standard_normal(), 0.999))
+        for k in range(max_tries):
+            c = layers.coef[i].copy()
+            amp = 0.02 * 0.5 ** (k // 20)
+            c[:, 1:] *= 1.0 + amp * rng.standard_normal(c[:, 1:].shape)
+            if positivity_ok(c):
+                break
+        else:
+            raise RuntimeError(f"no valid target set for layer {i}")
+        coefs.append(c)
+    return LayerSet(layers.name + "_target", np.array(taus), np.array(omegas), coefs, list(layers.N),
+                    list(layers.L), list(layers.M), list(layers.n_dphi), [])
