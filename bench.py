@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=5, help="replays of the hipGraph timed beside the headline")
     ap.add_argument("--precision", choices=["fp64", "fp32_refined"], default="fp64",
                     help="arithmetic of the boundary solves of the timed path")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default schedule and tile shape instead of running the autotuner first")
     ap.add_argument("--compare-steps", type=int, default=3,
                     help="solves of the other precision timed for the comparison block (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -243,6 +245,10 @@ def main():
     status = torch.empty(layers.n_layers, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    tuning = None
+    if not args.no_autotune:  # the library's autotuner picks the eigensolver schedule and tile shape
+        tuning = plan.autotune(tau, omega, coef, F, status, stream.cuda_stream)
+        print(f"autotuned: {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         plan.solve(tau, omega, coef, F, status, stream.cuda_stream)
     torch.cuda.synchronize()
@@ -277,6 +283,8 @@ def main():
     try:
         gplan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, precision=prec_code[args.precision],
                              flags=binding.FLAG_GRAPH)
+        if tuning:
+            gplan.set_tuning(tuning["eigen_schedule"], tuning["trsm_rows"])
         gstream = torch.cuda.Stream()
         Fg = torch.empty_like(F)
         with torch.cuda.stream(gstream):
@@ -300,6 +308,8 @@ def main():
     if args.compare_steps > 0:
         other = "fp32_refined" if args.precision == "fp64" else "fp64"
         cplan = binding.Plan(layers.N, layers.L, layers.M, layers.n_dphi, precision=prec_code[other])
+        if tuning:
+            cplan.set_tuning(tuning["eigen_schedule"], tuning["trsm_rows"])
         Fc = torch.empty_like(F)
         sc = torch.empty_like(status)
         cplan.solve(tau, omega, coef, Fc, sc, stream.cuda_stream)
@@ -352,6 +362,7 @@ def main():
         "err_layers_checked": n_checked,
         "physical_rhs_per_s": sum(m * 4 * n for m, n in zip(layers.M, layers.N)) / (ms / 1e3),
         "plan_ms": plan_ms,
+        "tuning": tuning,
         "roofline": roofline,
         "graph_ms_per_step": graph_ms,
         "compare": compare,

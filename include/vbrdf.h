@@ -194,6 +194,33 @@ const char* vbrdf_stage_name(int32_t i);
 vbrdf_status vbrdf_backward(vbrdf_plan* plan, const double* tau, const double* omega, const double* coef,
                             const double* dF_r, double* dtau, double* domega, double* dcoef, void* stream);
 
+/* Scheduling and tile choices of a plan: how the eigensolver's workgroups take the (layer, order)
+ * problems, and the rows per tile of the FP64 right divisions. Results do not depend on them (every
+ * problem is solved by the same arithmetic); only the time does. */
+#define VBRDF_EIGEN_PLAN_ORDER 0    /* one workgroup per problem, in plan order (default) */
+#define VBRDF_EIGEN_LONGEST_FIRST 1 /* one workgroup per problem, largest systems first */
+#define VBRDF_EIGEN_PERSISTENT 2    /* one workgroup per compute unit taking problems from a queue,
+                                       largest first, until none is left */
+typedef struct vbrdf_tuning {
+  int32_t eigen_schedule; /* VBRDF_EIGEN_* */
+  int32_t trsm_rows;      /* 4, 8 (default) or 16 right-hand-side rows per right-division tile */
+} vbrdf_tuning;
+
+/* Current choices of the plan (host call). */
+vbrdf_status vbrdf_plan_get_tuning(const vbrdf_plan* plan, vbrdf_tuning* out);
+
+/* Set the choices (INVALID for values outside the lists above). A captured graph is recaptured at
+ * the next solve. */
+vbrdf_status vbrdf_plan_set_tuning(vbrdf_plan* plan, const vbrdf_tuning* tuning);
+
+/* Autotuner: enqueues solves of the given inputs with each candidate schedule and tile shape,
+ * times the eigensolver stage and the right-division stage with hipEvents on `stream` (waiting
+ * for them), and keeps the fastest choice of each. Synchronous. Afterwards F_r and layer_status
+ * hold the result of one more solve with the chosen configuration. `chosen` (host, may be NULL) receives the choice.
+ * Errors as for vbrdf_solve, plus DEVICE. */
+vbrdf_status vbrdf_plan_autotune(vbrdf_plan* plan, const double* tau, const double* omega, const double* coef,
+                                 double* F_r, int32_t* layer_status, void* stream, vbrdf_tuning* chosen);
+
 /* Stokes radiances of eq. 1: for a beam of Stokes vector I0 (host array of 4) incident on node q
  * at azimuth phi0 (radians), I_out[i][k][r] = mu_q sum_p F_r(i <- q, phi_k - phi0)[r][p] I0[p],
  * the upward radiance at the top towards (-mu_i, phi_k = 2 pi k / n_dphi). When phi0 lies on the

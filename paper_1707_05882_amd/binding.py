@@ -39,8 +39,16 @@ EXPORTED = (
     "vbrdf_abi_version", "vbrdf_last_error", "vbrdf_gauss_nodes", "vbrdf_plan_create",
     "vbrdf_workspace_query", "vbrdf_plan_destroy", "vbrdf_plan_output_bytes", "vbrdf_plan_workspace_bytes",
     "vbrdf_solve", "vbrdf_plan_inspect", "vbrdf_radiance", "vbrdf_plan_stage_times", "vbrdf_stage_name",
-    "vbrdf_solve_noalloc", "vbrdf_backward",
+    "vbrdf_solve_noalloc", "vbrdf_backward", "vbrdf_plan_get_tuning", "vbrdf_plan_set_tuning",
+    "vbrdf_plan_autotune",
 )
+EIGEN_PLAN_ORDER = 0
+EIGEN_LONGEST_FIRST = 1
+EIGEN_PERSISTENT = 2
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("eigen_schedule", ctypes.c_int32), ("trsm_rows", ctypes.c_int32)]
 
 
 class VbrdfError(RuntimeError):
@@ -109,6 +117,12 @@ def load():
     L.vbrdf_solve_noalloc.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
     L.vbrdf_backward.restype = i32
     L.vbrdf_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.vbrdf_plan_get_tuning.restype = i32
+    L.vbrdf_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.vbrdf_plan_set_tuning.restype = i32
+    L.vbrdf_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.vbrdf_plan_autotune.restype = i32
+    L.vbrdf_plan_autotune.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Tuning)]
     if L.vbrdf_abi_version() != ABI_VERSION:
         raise OSError("libvbrdf.so ABI version mismatch")
     _lib = L
@@ -214,6 +228,22 @@ class Plan:
     def solve(self, tau, omega, coef, F_r, layer_status, stream=0):
         _check(load().vbrdf_solve(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(F_r), _ptr(layer_status),
                                   ctypes.c_void_p(int(stream))))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(load().vbrdf_plan_get_tuning(self._h, ctypes.byref(t)))
+        return {"eigen_schedule": t.eigen_schedule, "trsm_rows": t.trsm_rows}
+
+    def set_tuning(self, eigen_schedule, trsm_rows):
+        t = Tuning(int(eigen_schedule), int(trsm_rows))
+        _check(load().vbrdf_plan_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, tau, omega, coef, F_r, layer_status, stream=0):
+        """Time the candidate schedules and tile shapes on these inputs and keep the fastest."""
+        t = Tuning()
+        _check(load().vbrdf_plan_autotune(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(F_r),
+                                          _ptr(layer_status), ctypes.c_void_p(int(stream)), ctypes.byref(t)))
+        return {"eigen_schedule": t.eigen_schedule, "trsm_rows": t.trsm_rows}
 
     def backward(self, tau, omega, coef, dF, dtau, domega, dcoef, stream=0):
         """Gradients of a loss with respect to tau, omega and coef given dLoss/dF_r (device

@@ -136,6 +136,8 @@ struct vbrdf_plan : LaunchSet {
     if (quad_d) (void)hipFree(const_cast<double*>(quad_d));
     if (ws_d && ws_owned) (void)hipFree(ws_d);
     if (status_d) (void)hipFree(status_d);
+    if (order_d) (void)hipFree(const_cast<int32_t*>(order_d));
+    if (queue_d) (void)hipFree(queue_d);
   }
 };
 
@@ -155,6 +157,13 @@ vbrdf_status vbrdf_gauss_nodes(int32_t N, double* mu, double* alpha) {
     alpha[i] = 0.5 * w[i];
   }
   return VBRDF_OK;
+}
+
+// Right-division tile rows of a plan (4, 8 or 16) and the matching grid and LDS size.
+static void set_trsm_rows(LaunchSet* p, int rows) {
+  p->trsm_rows = rows;
+  p->trsm_tiles = trsm_tiles_for(p->max_n, rows);
+  p->trsm_lds = trsm_lds_for(p->max_n, rows);
 }
 
 // Descriptor checks shared by plan creation and the workspace query.
@@ -248,8 +257,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     for (int i = 0; i < ly.N; ++i)
       for (int q = 0; q < ly.N; ++q) tasks.push_back(SynthTask{l, i, q, 0});
     p->max_n = std::max(p->max_n, n);
-    p->trsm_tiles = std::max(p->trsm_tiles, (n + kTrsmRows - 1) / kTrsmRows);
-    p->trsm_lds = std::max(p->trsm_lds, sizeof(double) * (size_t)n * (trsm_ldb(n) + 2));
+    p->trsm32_tiles = std::max(p->trsm32_tiles, (n + kTrsmRows - 1) / kTrsmRows);
     p->max_N = std::max(p->max_N, ly.N);
     coef_off += 6 * (int64_t)ly.L;
     out_off += (int64_t)ly.N * ly.N * ly.n_dphi * 16;
@@ -284,10 +292,30 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
   p->tasks_d = tasks_d;
   if (st == VBRDF_OK) st = upload(quad, &quad_d);
   p->quad_d = quad_d;
+  if (st == VBRDF_OK) {  // eigensolver work order: largest systems first (stable)
+    std::vector<int32_t> order(p->items_h.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return p->items_h[a].n > p->items_h[b].n; });
+    int32_t* order_d = nullptr;
+    st = upload(order, &order_d);
+    p->order_d = order_d;
+  }
+  if (st == VBRDF_OK) {
+    std::vector<int32_t> zero(1, 0);
+    st = upload(zero, &p->queue_d);
+  }
   if (st != VBRDF_OK) {
     delete p;
     return st;
   }
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      p->persist_groups = cus;
+  }
+  p->eigen_mode = kEigenPlanOrder;
   p->graph = (d->flags & VBRDF_FLAG_GRAPH) != 0;
   p->precision = d->precision;
   p->transmission = (d->flags & VBRDF_FLAG_EMIT_TRANSMISSION) != 0;
@@ -319,9 +347,12 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       }
     }
   }
-  if (p->trsm_lds > 65536) {  // the right-division tile of a large system exceeds the default LDS cap
+  set_trsm_rows(p, kTrsmRows);
+  size_t lds_max = 0;
+  for (int rows : {4, 8, 16}) lds_max = std::max(lds_max, trsm_lds_for(p->max_n, rows));
+  if (lds_max > 65536) {  // the right-division tile of a large system exceeds the default LDS cap
     const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trsm),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->trsm_lds);
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
     if (ea != hipSuccess) {
       delete p;
       return fail(VBRDF_E_DEVICE, "hipFuncSetAttribute(k_trsm): %s", hipGetErrorString(ea));
@@ -384,7 +415,14 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   const dim3 gg(gt, gt, ni);
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufE, kBufG, 0, layer_status);  // G = F~ E~
   mark();
-  k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap);
+  if (p->eigen_mode == kEigenPersistent && p->queue_d && p->order_d) {
+    k_reset_counter<<<1, 1, 0, s>>>(p->queue_d);
+    k_eigen<<<std::min(ni, p->persist_groups), kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status,
+                                                                      p->qr_sweep_cap, p->order_d, p->queue_d, ni);
+  } else {
+    const int32_t* ord = p->eigen_mode == kEigenPlanOrder ? nullptr : p->order_d;
+    k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, ord, nullptr, ni);
+  }
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, kBufX, kBufG, kGemmTransA, layer_status);  // U' = Z X
   mark();
@@ -399,8 +437,8 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, layer_status);  // U^T
   k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, LuBufs{{kBufX, kBufX}, {kBufYS, kBufYS}});
   k_trsm<<<xcd_grid(ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(
-      p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status,
-      TrsmBufs{{kBufYS, kBufYS}, {kBufZ, kBufZ}, {kBufG, kBufG}, 1});  // Y^T = (G U)^T U^-T
+      p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, TrsmBufs{{kBufYS, kBufYS}, {kBufZ, kBufZ}, {kBufG, kBufG}, 1},
+      p->trsm_rows);  // Y^T = (G U)^T U^-T
   k_refine_lam<<<dim3((mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   k_refine_close<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
   k_refine_pairs<<<dim3((mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
@@ -419,6 +457,7 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   const LuBufs lub{{kBufZ, kBufX}, {kBufG, kBufF}, 0};
   const TrsmBufs trb{{kBufG, kBufF}, {kBufU, kBufU}, {kBufYS, kBufYT}, 2, 0};  // U S'^-1, U T'^-1
   const dim3 xg(xcd_grid(2 * ni, p->trsm_tiles));
+  const dim3 xg32(xcd_grid(2 * ni, p->trsm32_tiles));
   if (p->precision == VBRDF_PRECISION_FP32_REFINED) {
     // FP32 factorisations and right divisions, refined against FP64 residuals; sides that do not
     // converge are redone in FP64 (or reported NONCONVERGED when the fallback is disabled)
@@ -426,10 +465,10 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
     const dim3 rg(gt, gt, 2 * ni);
     k_lu32<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status);
     mark();
-    k_trsm32<<<xg, 64, lds32, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, 0);
+    k_trsm32<<<xg32, 64, lds32, s>>>(p->items_d, ni, p->trsm32_tiles, p->ws_d, layer_status, 0);
     for (int r = 0; r < p->refine_steps; ++r) {
       k_resid<<<rg, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
-      k_trsm32<<<xg, 64, lds32, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, 1);
+      k_trsm32<<<xg32, 64, lds32, s>>>(p->items_d, ni, p->trsm32_tiles, p->ws_d, layer_status, 1);
     }
     k_resid<<<rg, 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
     k_bcheck<<<ni, 64, 0, s>>>(p->items_d, p->ws_d, layer_status, p->no_fallback ? 1 : 0);
@@ -438,12 +477,12 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
     TrsmBufs tf = trb;
     tf.only_flagged = 1;
     k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, lf);
-    k_trsm<<<xg, 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, tf);
+    k_trsm<<<xg, 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, tf, p->trsm_rows);
     mark();
   } else {
     k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, lub);
     mark();
-    k_trsm<<<xg, 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, trb);
+    k_trsm<<<xg, 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, trb, p->trsm_rows);
     mark();
   }
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status,
@@ -471,8 +510,9 @@ void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omeg
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, st);
   k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, stw, LuBufs{{kBufX, kBufX}, {kBufG, kBufG}, 0});
   k_fill_identity<<<dim3((mn * mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufF, st);
-  k_trsm<<<xcd_grid(ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, stw,
-                                                              TrsmBufs{{kBufG, kBufG}, {kBufF, kBufF}, {kBufW, kBufW}, 1, 0});
+  k_trsm<<<xcd_grid(ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(
+      p->items_d, ni, p->trsm_tiles, p->ws_d, stw, TrsmBufs{{kBufG, kBufG}, {kBufF, kBufF}, {kBufW, kBufW}, 1, 0},
+      p->trsm_rows);
   gemm(kBufYS, kBufE, kBufT1, kGemmTransA);                 // P_s^T Q
   gemm(kBufT1, kBufYS, kBufT2, kGemmTransB | kGemmNegate);  // A_s-bar
   gemm(kBufYT, kBufE, kBufT1, kGemmTransA);
@@ -583,6 +623,86 @@ int32_t vbrdf_plan_stage_times(vbrdf_plan* p, float* ms_out, int32_t cap) {
 }
 
 const char* vbrdf_stage_name(int32_t i) { return (i >= 0 && i < kNumStages) ? kStageNames[i] : nullptr; }
+
+vbrdf_status vbrdf_plan_get_tuning(const vbrdf_plan* p, vbrdf_tuning* out) {
+  if (!p || !out) return fail(VBRDF_E_INVALID, "null pointer");
+  out->eigen_schedule = p->eigen_mode;
+  out->trsm_rows = p->trsm_rows;
+  return VBRDF_OK;
+}
+
+vbrdf_status vbrdf_plan_set_tuning(vbrdf_plan* p, const vbrdf_tuning* t) {
+  if (!p || !t) return fail(VBRDF_E_INVALID, "null pointer");
+  if (t->eigen_schedule < kEigenPlanOrder || t->eigen_schedule > kEigenPersistent)
+    return fail(VBRDF_E_INVALID, "unknown eigen schedule %d", t->eigen_schedule);
+  if (t->trsm_rows != 4 && t->trsm_rows != 8 && t->trsm_rows != 16)
+    return fail(VBRDF_E_INVALID, "trsm_rows must be 4, 8 or 16 (got %d)", t->trsm_rows);
+  p->eigen_mode = t->eigen_schedule;
+  set_trsm_rows(p, t->trsm_rows);
+  if (p->gexec) {  // the captured launch sequence no longer matches
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  return VBRDF_OK;
+}
+
+vbrdf_status vbrdf_plan_autotune(vbrdf_plan* p, const double* tau, const double* omega, const double* coef,
+                                 double* F_r, int32_t* layer_status, void* stream, vbrdf_tuning* chosen) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<hipEvent_t> ev(kNumSolveStages + 1, nullptr);
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  const int eig_stage = 4, refine_stage = 7, trsm_stage = 13;  // positions in kStageNames
+  const int row_stage = p->precision == VBRDF_PRECISION_FP32_REFINED ? refine_stage : trsm_stage;
+  const int cand_e[3] = {kEigenPlanOrder, kEigenLongestFirst, kEigenPersistent};
+  const int cand_r[3] = {4, 8, 16};
+  float best_e = 1e30f, best_r = 1e30f;
+  int pick_e = p->eigen_mode, pick_r = p->trsm_rows;
+  vbrdf_status st = VBRDF_OK;
+  for (int round = 0; round < 2 && st == VBRDF_OK; ++round) {  // round 0 warms every variant up
+    for (int c = 0; c < 3; ++c) {
+      p->eigen_mode = cand_e[c];
+      set_trsm_rows(p, cand_r[c]);
+      enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s, ev.data());
+      hipError_t e = hipEventSynchronize(ev[kNumSolveStages]);
+      float te = 0.0f, tr = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&te, ev[eig_stage], ev[eig_stage + 1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&tr, ev[row_stage], ev[row_stage + 1]);
+      if (e != hipSuccess) {
+        st = fail(VBRDF_E_DEVICE, "autotune timing: %s", hipGetErrorString(e));
+        break;
+      }
+      if (round == 1 && te < best_e) {
+        best_e = te;
+        pick_e = cand_e[c];
+      }
+      if (round == 1 && tr < best_r) {
+        best_r = tr;
+        pick_r = cand_r[c];
+      }
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  p->eigen_mode = pick_e;
+  set_trsm_rows(p, pick_r);
+  if (st == VBRDF_OK) {  // leave the result of the chosen configuration behind
+    enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s, nullptr);
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(VBRDF_E_DEVICE, "autotune: %s", hipGetErrorString(e));
+  }
+  p->solved = true;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  if (st != VBRDF_OK) return st;
+  if (chosen) {
+    chosen->eigen_schedule = pick_e;
+    chosen->trsm_rows = pick_r;
+  }
+  return VBRDF_OK;
+}
 
 vbrdf_status vbrdf_backward(vbrdf_plan* p, const double* tau, const double* omega, const double* coef,
                             const double* dF_r, double* dtau, double* domega, double* dcoef, void* stream) {

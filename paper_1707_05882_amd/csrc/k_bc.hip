@@ -281,11 +281,11 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
 // TF: type of the factor and of the arithmetic (double, or float in the refined path); TB: type
 // of the right-hand side rows (the FP64 U, or an FP32 residual); kAdd: accumulate into Y instead of
 // overwriting it. The right-hand side of side `which` is read at rhs_off doubles from the item base.
-template <int ldb, typename TF, typename TB, bool kAdd>
+// R: right-hand-side rows per tile (64 / R lanes per row).
+template <int R, int ldb, typename TF, typename TB, bool kAdd>
 __device__ __forceinline__ void trsm_tile(const Item& it, int which, int r0, double* ws, const TF* __restrict__ AT,
                                           const TB* __restrict__ U, double* __restrict__ Y) {
   const int n = it.n, lane = threadIdx.x;
-  constexpr int R = kTrsmRows;
   double* base = ws + it.ws;
   double* ex = base + extras_off(n);
   const double* __restrict__ id = lu_invd(ex, n, which);
@@ -375,13 +375,13 @@ __device__ __forceinline__ void trsm_tile(const Item& it, int which, int r0, dou
 }
 
 __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status,
-                                             TrsmBufs b) {
+                                             TrsmBufs b, int rows) {
   int g, tile;
   xcd_split(blockIdx.x, tiles, g, tile);  // g = sides item + side; the tiles of one matrix share an XCD
   if (g >= b.sides * n_items) return;
   const Item it = items[g / b.sides];
   if (status[it.layer] != 0) return;
-  const int r0 = tile * kTrsmRows;
+  const int r0 = tile * rows;
   if (r0 >= it.n) return;
   const int side = g % b.sides;
   const int n = it.n;
@@ -390,11 +390,16 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
   const double* AT = buf_ptr(ws, it, b.a[side]);
   const double* U = buf_ptr(ws, it, b.rhs[side]);
   double* Y = buf_ptr(ws, it, b.y[side]);
-  // the tile stride is a compile-time constant so that LDS offsets fold into the instructions
-  if (trsm_ldb(n) == kTrsmLdb)
-    trsm_tile<kTrsmLdb, double, double, false>(it, side, r0, ws, AT, U, Y);
+  // the tile shape and stride are compile-time constants so that LDS offsets fold into the
+  // instructions; the plan picks the rows per tile (autotuned, 8 by default)
+  if (rows == 4)
+    trsm_tile<4, 5, double, double, false>(it, side, r0, ws, AT, U, Y);
+  else if (rows == 16)
+    trsm_tile<16, 17, double, double, false>(it, side, r0, ws, AT, U, Y);
+  else if (trsm_ldb(n) == kTrsmLdb)
+    trsm_tile<kTrsmRows, kTrsmLdb, double, double, false>(it, side, r0, ws, AT, U, Y);
   else
-    trsm_tile<kTrsmRows + 1, double, double, false>(it, side, r0, ws, AT, U, Y);
+    trsm_tile<kTrsmRows, kTrsmRows + 1, double, double, false>(it, side, r0, ws, AT, U, Y);
 }
 
 // Columns of V = E~ U that lost more than ~7 digits to cancellation (the conservation mode of
@@ -659,10 +664,10 @@ __global__ __launch_bounds__(64) void k_trsm32(const Item* items, int n_items, i
   double* Y = base + (int64_t)(side == 0 ? kBufYS : kBufYT) * n * n;
   if (accumulate) {
     const float* R = reinterpret_cast<const float*>(base + (int64_t)kBufE * n * n) + (int64_t)side * n * n;
-    trsm_tile<kTrsmRows + 1, float, float, true>(it, side, r0, ws, AT, R, Y);
+    trsm_tile<kTrsmRows, kTrsmRows + 1, float, float, true>(it, side, r0, ws, AT, R, Y);
   } else {
     const double* U = base + (int64_t)kBufU * n * n;
-    trsm_tile<kTrsmRows + 1, float, double, false>(it, side, r0, ws, AT, U, Y);
+    trsm_tile<kTrsmRows, kTrsmRows + 1, float, double, false>(it, side, r0, ws, AT, U, Y);
   }
 }
 

@@ -1231,21 +1231,36 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
 }
 
 __global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, double* ws, int32_t* status,
-                                                          int sweep_cap) {
-  const Item it = items[blockIdx.x];
-  if (status[it.layer] != 0) return;
+                                                          int sweep_cap, const int32_t* order, int32_t* queue,
+                                                          int n_items) {
   __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1) + 3 * 64];
   __shared__ double srefl[2 * 3 * kMaxn];
   __shared__ double sred[16];
   __shared__ int sctl[8];
   __shared__ double sxyz[3];
   __shared__ ZOp zops[2];
-  double* base = ws + it.ws;
-  if (it.n <= kLdsMaxn)
-    eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
-  else
-    eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+  __shared__ int snext;
+  for (int pos = blockIdx.x;;) {
+    if (queue) {  // persistent: take the next position (every wave exits once all are taken)
+      __syncthreads();
+      if (threadIdx.x == 0) snext = atomicAdd(queue, 1);
+      __syncthreads();
+      pos = snext;
+    }
+    if (pos >= n_items) return;
+    const Item it = items[order ? order[pos] : pos];
+    if (status[it.layer] == 0) {
+      double* base = ws + it.ws;
+      if (it.n <= kLdsMaxn)
+        eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+      else
+        eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+    }
+    if (!queue) return;
+  }
 }
+
+__global__ void k_reset_counter(int32_t* counter) { *counter = 0; }
 
 // U = Q U' for the reflectors of the Hessenberg reduction, Q = H_0 H_1 ... H_{n-3} with
 // H_k = I - tau_k v_k v_k^T on rows k+1..n-1 (v_k and tau_k left in the workspace by k_eigen):

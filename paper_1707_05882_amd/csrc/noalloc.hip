@@ -170,8 +170,11 @@ extern "C" vbrdf_status vbrdf_solve_noalloc(int32_t N, int32_t L, int32_t M, int
   ls.n_tasks = N * N;
   ls.max_n = n;
   ls.max_N = N;
+  ls.trsm_rows = kTrsmRows;
   ls.trsm_tiles = (n + kTrsmRows - 1) / kTrsmRows;
+  ls.trsm32_tiles = ls.trsm_tiles;
   ls.trsm_lds = trsm_lds;
+  ls.eigen_mode = kEigenPlanOrder;  // one layer: every order has the same size
   enqueue_solve(ls, tau, omega, coef, F_r, layer_status, s, nullptr);
   e = hipGetLastError();
   if (e != hipSuccess) return vbrdf_fail(VBRDF_E_DEVICE, "launch: %s", hipGetErrorString(e));

@@ -95,8 +95,14 @@ __global__ void k_assemble(const Item* items, const Layer* layers, const double*
 // negated, or added to the existing C)
 constexpr int kGemmTransA = 1, kGemmTransB = 2, kGemmTransC = 4, kGemmNegate = 8, kGemmAccumulate = 16;
 __global__ void k_gemm(const Item* items, double* ws, int bufA, int bufB, int bufC, int mode, const int32_t* status);
-// sweep_cap: largest number of QR sweeps per problem (above it the layer is NUMERIC), 0 = default
-__global__ void k_eigen(const Item* items, double* ws, int32_t* status, int sweep_cap);
+// sweep_cap: largest number of QR sweeps per problem (above it the layer is NUMERIC), 0 = default.
+// order: item permutation (workgroup b solves items[order[b]]), or null for the plan order. queue:
+// when not null, the launch is persistent: each workgroup takes the next position of `order`
+// from this counter (reset to 0 before the launch) until n_items are taken.
+constexpr int kEigenPlanOrder = 0, kEigenLongestFirst = 1, kEigenPersistent = 2;
+__global__ void k_eigen(const Item* items, double* ws, int32_t* status, int sweep_cap, const int32_t* order,
+                        int32_t* queue, int n_items);
+__global__ void k_reset_counter(int32_t* counter);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
@@ -137,7 +143,8 @@ __global__ void k_trsm32(const Item* items, int n_items, int tiles, double* ws, 
 __global__ void k_resid(const Item* items, double* ws, const int32_t* status);
 __global__ void k_bcheck(const Item* items, double* ws, int32_t* status, int no_fallback);
 __global__ void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b);
-__global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status, TrsmBufs b);
+__global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status, TrsmBufs b,
+                       int rows);
 // Eigenpair refinement of the homogeneous step (between the eigenvector back-transformation and the
 // mode vectors): transposed copy, per-column update of the eigenvalues, correction matrix, commit.
 __global__ void k_transpose(const Item* items, double* ws, int src, int dst, const int32_t* status);
@@ -156,6 +163,13 @@ constexpr int kTrsmRows = 8;
 constexpr int kTrsmLdb = 18;
 static_assert(kTrsmLdb > kTrsmRows, "the tile row holds kTrsmRows entries");
 __host__ __device__ inline int trsm_ldb(int n) { return n <= kLdsMaxn ? kTrsmLdb : kTrsmRows + 1; }
+// LDS row stride of the FP64 right-division tile for `rows` rows per tile (4, 8 or 16).
+__host__ __device__ inline int trsm_ldb_rows(int n, int rows) { return rows == 8 ? trsm_ldb(n) : rows + 1; }
+// Right-division tile geometry for `rows` rows per tile over systems up to max_n.
+inline int trsm_tiles_for(int max_n, int rows) { return (max_n + rows - 1) / rows; }
+inline size_t trsm_lds_for(int max_n, int rows) {
+  return sizeof(double) * (size_t)max_n * (trsm_ldb_rows(max_n, rows) + 2);
+}
 
 // XCD-aware launch order: workgroups are dealt round-robin to the 8 XCDs (each with its own L2),
 // so the `tiles` workgroups that read one matrix get linear ids that agree mod 8. For `groups`
@@ -183,8 +197,14 @@ struct LaunchSet {
   double* ws_d = nullptr;          // per-item workspace blocks
   int n_layers = 0, n_items = 0, n_tasks = 0;
   int max_n = 0, max_N = 0;
-  int trsm_tiles = 0;   // row tiles of the right division (largest item)
-  size_t trsm_lds = 0;  // its LDS bytes
+  int trsm_rows = kTrsmRows;  // right-hand-side rows per FP64 right-division tile (4, 8, 16)
+  int trsm_tiles = 0;         // row tiles of the FP64 right division (largest item)
+  size_t trsm_lds = 0;        // its LDS bytes
+  int trsm32_tiles = 0;       // row tiles of the FP32 right division (kTrsmRows rows each)
+  int eigen_mode = 0;         // k_eigen scheduling: kEigenPlanOrder / kEigenLongestFirst / kEigenPersistent
+  const int32_t* order_d = nullptr;  // items by decreasing size (longest first)
+  int32_t* queue_d = nullptr;        // work counter of the persistent eigensolver
+  int persist_groups = 256;          // workgroups of the persistent eigensolver (compute units)
   int qr_sweep_cap = 0;       // 0 = the eigensolver's default
   bool transmission = false;  // also write the per-order transmission T^m
   int precision = 0;          // VBRDF_PRECISION_*

@@ -119,3 +119,12 @@ def test_radiance_and_inspect_reject_a_null_plan():
     assert lib.vbrdf_radiance(None, None, 0, 0, 0.0, i0, None, None) == binding.E_INVALID
     assert lib.vbrdf_plan_inspect(None, 0, 0, None, None, None, None, None) == binding.E_INVALID
     assert lib.vbrdf_plan_stage_times(None, None, 0) == binding.E_INVALID
+
+
+def test_tuning_calls_reject_bad_arguments():
+    lib = binding.load()
+    t = binding.Tuning(0, 8)
+    assert lib.vbrdf_plan_get_tuning(None, ctypes.byref(t)) == binding.E_INVALID
+    assert lib.vbrdf_plan_set_tuning(None, ctypes.byref(t)) == binding.E_INVALID
+    assert lib.vbrdf_plan_autotune(None, None, None, None, None, None, None, None) == binding.E_INVALID
+    assert lib.vbrdf_backward(None, None, None, None, None, None, None, None, None) == binding.E_INVALID
