@@ -348,11 +348,11 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     }
   }
   set_trsm_rows(p, kTrsmRows);
-  size_t lds_max = 0;
-  for (int rows : {4, 8, 16}) lds_max = std::max(lds_max, trsm_lds_for(p->max_n, rows));
-  if (lds_max > 65536) {  // the right-division tile of a large system exceeds the default LDS cap
-    const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_trsm),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_max);
+  for (int rows : {4, 8, 16}) {
+    const size_t lds = trsm_lds_for(p->max_n, rows);
+    if (lds <= 65536) continue;  // the right-division tile of a large system exceeds the default LDS cap
+    const hipError_t ea = hipFuncSetAttribute(trsm_kernel_ptr(rows), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)lds);
     if (ea != hipSuccess) {
       delete p;
       return fail(VBRDF_E_DEVICE, "hipFuncSetAttribute(k_trsm): %s", hipGetErrorString(ea));
@@ -417,11 +417,11 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   mark();
   if (p->eigen_mode == kEigenPersistent && p->queue_d && p->order_d) {
     k_reset_counter<<<1, 1, 0, s>>>(p->queue_d);
-    k_eigen<<<std::min(ni, p->persist_groups), kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status,
-                                                                      p->qr_sweep_cap, p->order_d, p->queue_d, ni);
+    k_eigen_persistent<<<std::min(ni, p->persist_groups), kEigenThreads, 0, s>>>(
+        p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, p->order_d, p->queue_d, ni);
   } else {
     const int32_t* ord = p->eigen_mode == kEigenPlanOrder ? nullptr : p->order_d;
-    k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, ord, nullptr, ni);
+    k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, ord);
   }
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, kBufX, kBufG, kGemmTransA, layer_status);  // U' = Z X
@@ -436,9 +436,8 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufG, kBufZ, kGemmTransC, layer_status);  // (F~ E~ U)^T
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, layer_status);  // U^T
   k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, LuBufs{{kBufX, kBufX}, {kBufYS, kBufYS}});
-  k_trsm<<<xcd_grid(ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(
-      p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, TrsmBufs{{kBufYS, kBufYS}, {kBufZ, kBufZ}, {kBufG, kBufG}, 1},
-      p->trsm_rows);  // Y^T = (G U)^T U^-T
+  launch_trsm(p->trsm_rows, dim3(xcd_grid(ni, p->trsm_tiles)), p->trsm_lds, s, p->items_d, ni, p->trsm_tiles,
+              p->ws_d, layer_status, TrsmBufs{{kBufYS, kBufYS}, {kBufZ, kBufZ}, {kBufG, kBufG}, 1, 0});  // Y^T = (G U)^T U^-T
   k_refine_lam<<<dim3((mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
   k_refine_close<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
   k_refine_pairs<<<dim3((mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
@@ -477,12 +476,12 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
     TrsmBufs tf = trb;
     tf.only_flagged = 1;
     k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, lf);
-    k_trsm<<<xg, 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, tf, p->trsm_rows);
+    launch_trsm(p->trsm_rows, xg, p->trsm_lds, s, p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, tf);
     mark();
   } else {
     k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, lub);
     mark();
-    k_trsm<<<xg, 64, p->trsm_lds, s>>>(p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, trb, p->trsm_rows);
+    launch_trsm(p->trsm_rows, xg, p->trsm_lds, s, p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, trb);
     mark();
   }
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status,
@@ -510,9 +509,8 @@ void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omeg
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, st);
   k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, stw, LuBufs{{kBufX, kBufX}, {kBufG, kBufG}, 0});
   k_fill_identity<<<dim3((mn * mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufF, st);
-  k_trsm<<<xcd_grid(ni, p->trsm_tiles), 64, p->trsm_lds, s>>>(
-      p->items_d, ni, p->trsm_tiles, p->ws_d, stw, TrsmBufs{{kBufG, kBufG}, {kBufF, kBufF}, {kBufW, kBufW}, 1, 0},
-      p->trsm_rows);
+  launch_trsm(p->trsm_rows, dim3(xcd_grid(ni, p->trsm_tiles)), p->trsm_lds, s, p->items_d, ni, p->trsm_tiles, p->ws_d,
+              stw, TrsmBufs{{kBufG, kBufG}, {kBufF, kBufF}, {kBufW, kBufW}, 1, 0});
   gemm(kBufYS, kBufE, kBufT1, kGemmTransA);                 // P_s^T Q
   gemm(kBufT1, kBufYS, kBufT2, kGemmTransB | kGemmNegate);  // A_s-bar
   gemm(kBufYT, kBufE, kBufT1, kGemmTransA);

@@ -374,14 +374,15 @@ __device__ __forceinline__ void trsm_tile(const Item& it, int which, int r0, dou
   }
 }
 
+template <int kRows>
 __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status,
-                                             TrsmBufs b, int rows) {
+                                             TrsmBufs b) {
   int g, tile;
   xcd_split(blockIdx.x, tiles, g, tile);  // g = sides item + side; the tiles of one matrix share an XCD
   if (g >= b.sides * n_items) return;
   const Item it = items[g / b.sides];
   if (status[it.layer] != 0) return;
-  const int r0 = tile * rows;
+  const int r0 = tile * kRows;
   if (r0 >= it.n) return;
   const int side = g % b.sides;
   const int n = it.n;
@@ -391,15 +392,32 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
   const double* U = buf_ptr(ws, it, b.rhs[side]);
   double* Y = buf_ptr(ws, it, b.y[side]);
   // the tile shape and stride are compile-time constants so that LDS offsets fold into the
-  // instructions; the plan picks the rows per tile (autotuned, 8 by default)
-  if (rows == 4)
-    trsm_tile<4, 5, double, double, false>(it, side, r0, ws, AT, U, Y);
-  else if (rows == 16)
-    trsm_tile<16, 17, double, double, false>(it, side, r0, ws, AT, U, Y);
+  // instructions
+  if (kRows != 8)
+    trsm_tile<kRows, kRows + 1, double, double, false>(it, side, r0, ws, AT, U, Y);
   else if (trsm_ldb(n) == kTrsmLdb)
     trsm_tile<kTrsmRows, kTrsmLdb, double, double, false>(it, side, r0, ws, AT, U, Y);
   else
     trsm_tile<kTrsmRows, kTrsmRows + 1, double, double, false>(it, side, r0, ws, AT, U, Y);
+}
+template __global__ void k_trsm<4>(const Item*, int, int, double*, int32_t*, TrsmBufs);
+template __global__ void k_trsm<8>(const Item*, int, int, double*, int32_t*, TrsmBufs);
+template __global__ void k_trsm<16>(const Item*, int, int, double*, int32_t*, TrsmBufs);
+
+void launch_trsm(int rows, dim3 grid, size_t lds, hipStream_t s, const Item* items, int n_items, int tiles, double* ws,
+                 int32_t* status, TrsmBufs b) {
+  if (rows == 4)
+    k_trsm<4><<<grid, 64, lds, s>>>(items, n_items, tiles, ws, status, b);
+  else if (rows == 16)
+    k_trsm<16><<<grid, 64, lds, s>>>(items, n_items, tiles, ws, status, b);
+  else
+    k_trsm<8><<<grid, 64, lds, s>>>(items, n_items, tiles, ws, status, b);
+}
+
+const void* trsm_kernel_ptr(int rows) {
+  if (rows == 4) return reinterpret_cast<const void*>(&k_trsm<4>);
+  if (rows == 16) return reinterpret_cast<const void*>(&k_trsm<16>);
+  return reinterpret_cast<const void*>(&k_trsm<8>);
 }
 
 // Columns of V = E~ U that lost more than ~7 digits to cancellation (the conservation mode of

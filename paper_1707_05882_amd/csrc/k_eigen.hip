@@ -1230,9 +1230,30 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
 #undef ZZ
 }
 
+// One workgroup per problem: workgroup b solves items[order[b]] (order null: items[b]).
 __global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, double* ws, int32_t* status,
-                                                          int sweep_cap, const int32_t* order, int32_t* queue,
-                                                          int n_items) {
+                                                          int sweep_cap, const int32_t* order) {
+  const Item it = items[order ? order[blockIdx.x] : blockIdx.x];
+  if (status[it.layer] != 0) return;
+  __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1) + 3 * 64];
+  __shared__ double srefl[2 * 3 * kMaxn];
+  __shared__ double sred[16];
+  __shared__ int sctl[8];
+  __shared__ double sxyz[3];
+  __shared__ ZOp zops[2];
+  double* base = ws + it.ws;
+  if (it.n <= kLdsMaxn)
+    eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+  else
+    eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+}
+
+// Persistent form: every workgroup takes the next position of `order` from the counter `queue`
+// (reset to 0 before the launch) and solves that problem, until n_items are taken; every wave
+// reaches the exit once the counter passes n_items.
+__global__ __launch_bounds__(kEigenThreads) void k_eigen_persistent(const Item* items, double* ws, int32_t* status,
+                                                                     int sweep_cap, const int32_t* order,
+                                                                     int32_t* queue, int n_items) {
   __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1) + 3 * 64];
   __shared__ double srefl[2 * 3 * kMaxn];
   __shared__ double sred[16];
@@ -1240,23 +1261,19 @@ __global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, doub
   __shared__ double sxyz[3];
   __shared__ ZOp zops[2];
   __shared__ int snext;
-  for (int pos = blockIdx.x;;) {
-    if (queue) {  // persistent: take the next position (every wave exits once all are taken)
-      __syncthreads();
-      if (threadIdx.x == 0) snext = atomicAdd(queue, 1);
-      __syncthreads();
-      pos = snext;
-    }
+  for (;;) {
+    __syncthreads();  // the previous problem is done with the LDS
+    if (threadIdx.x == 0) snext = atomicAdd(queue, 1);
+    __syncthreads();
+    const int pos = snext;
     if (pos >= n_items) return;
-    const Item it = items[order ? order[pos] : pos];
-    if (status[it.layer] == 0) {
-      double* base = ws + it.ws;
-      if (it.n <= kLdsMaxn)
-        eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
-      else
-        eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
-    }
-    if (!queue) return;
+    const Item it = items[order[pos]];
+    if (status[it.layer] != 0) continue;
+    double* base = ws + it.ws;
+    if (it.n <= kLdsMaxn)
+      eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+    else
+      eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
   }
 }
 

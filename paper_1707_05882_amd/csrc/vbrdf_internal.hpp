@@ -96,12 +96,13 @@ __global__ void k_assemble(const Item* items, const Layer* layers, const double*
 constexpr int kGemmTransA = 1, kGemmTransB = 2, kGemmTransC = 4, kGemmNegate = 8, kGemmAccumulate = 16;
 __global__ void k_gemm(const Item* items, double* ws, int bufA, int bufB, int bufC, int mode, const int32_t* status);
 // sweep_cap: largest number of QR sweeps per problem (above it the layer is NUMERIC), 0 = default.
-// order: item permutation (workgroup b solves items[order[b]]), or null for the plan order. queue:
-// when not null, the launch is persistent: each workgroup takes the next position of `order`
-// from this counter (reset to 0 before the launch) until n_items are taken.
+// order: item permutation (workgroup b solves items[order[b]]), or null for the plan order. The
+// persistent form takes positions of `order` from the counter `queue` (reset to 0 before the
+// launch) until n_items are taken.
 constexpr int kEigenPlanOrder = 0, kEigenLongestFirst = 1, kEigenPersistent = 2;
-__global__ void k_eigen(const Item* items, double* ws, int32_t* status, int sweep_cap, const int32_t* order,
-                        int32_t* queue, int n_items);
+__global__ void k_eigen(const Item* items, double* ws, int32_t* status, int sweep_cap, const int32_t* order);
+__global__ void k_eigen_persistent(const Item* items, double* ws, int32_t* status, int sweep_cap,
+                                   const int32_t* order, int32_t* queue, int n_items);
 __global__ void k_reset_counter(int32_t* counter);
 __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
@@ -143,8 +144,13 @@ __global__ void k_trsm32(const Item* items, int n_items, int tiles, double* ws, 
 __global__ void k_resid(const Item* items, double* ws, const int32_t* status);
 __global__ void k_bcheck(const Item* items, double* ws, int32_t* status, int no_fallback);
 __global__ void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b);
-__global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status, TrsmBufs b,
-                       int rows);
+// one kernel per tile shape (rows per tile 4, 8 or 16); launch_trsm picks it
+template <int kRows>
+__global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status, TrsmBufs b);
+void launch_trsm(int rows, dim3 grid, size_t lds, hipStream_t s, const Item* items, int n_items, int tiles, double* ws,
+                 int32_t* status, TrsmBufs b);
+// the kernel instances, for attribute queries and settings
+const void* trsm_kernel_ptr(int rows);
 // Eigenpair refinement of the homogeneous step (between the eigenvector back-transformation and the
 // mode vectors): transposed copy, per-column update of the eigenvalues, correction matrix, commit.
 __global__ void k_transpose(const Item* items, double* ws, int src, int dst, const int32_t* status);
