@@ -122,6 +122,30 @@ class DifferentiableBRDF:
         return out
 
 
+class SpectralBRDF:
+    """Spectral batching: n_materials x n_wavelengths layers of one shape solved in one plan (one
+    launch per stage over every (material, wavelength, order) problem).
+
+    sb = SpectralBRDF(n_materials=8, n_wavelengths=9, N=32, L=64, M=64, n_dphi=32)
+    F = sb(tau, omega, coef)   # tau, omega: (n_materials, n_wavelengths); coef: (..., 6, L)
+    F[a][w]                    # (N, N, n_dphi, 4, 4) tensor of material a at wavelength w
+    """
+
+    def __init__(self, n_materials, n_wavelengths, N, L, M, n_dphi, device="cuda", precision="fp64"):
+        self.shape = (int(n_materials), int(n_wavelengths))
+        n = self.shape[0] * self.shape[1]
+        self.solver = BRDFSolver([N] * n, [L] * n, [M] * n, [n_dphi] * n, device=device,
+                                 precision=_PRECISIONS[precision])
+
+    def __call__(self, tau, omega, coef):
+        A, W = self.shape
+        tau = np.asarray(tau, dtype=np.float64).reshape(A * W)
+        omega = np.asarray(omega, dtype=np.float64).reshape(A * W)
+        coef = np.asarray(coef, dtype=np.float64).reshape(A * W, 6, -1)
+        views = self.solver(tau, omega, list(coef))
+        return [[views[a * W + w] for w in range(W)] for a in range(A)]
+
+
 _PRECISIONS = {"fp64": binding.PRECISION_FP64, "fp32_refined": binding.PRECISION_FP32_REFINED}
 
 

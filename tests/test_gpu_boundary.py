@@ -128,3 +128,19 @@ def test_python_brdf_entry_point():
     assert np.abs(F.cpu().numpy() - Fo).max() < TOL * np.abs(Fo[..., 0, 0]).max()
     Fs = api.brdf([1.2, 3.0], [0.93, 0.8], [coef, hg(88, 5)], [6, 4], [9, 5], [5, 3])
     assert len(Fs) == 2 and torch.equal(Fs[0], F)
+
+
+def test_spectral_batch_against_oracle():
+    """Spectral batching (materials x nine wavelengths in one plan): every (material, wavelength)
+    layer of a reduced spectral set against the oracle solved one layer at a time."""
+    from paper_1707_05882_amd.api import SpectralBRDF
+    from workloads import workload
+
+    w = workload("spectral", n_materials=2, N=8, L=12)
+    sb = SpectralBRDF(2, 9, 8, 12, 12, 32)
+    F = sb(np.reshape(w.tau, (2, 9)), np.reshape(w.omega, (2, 9)), np.reshape(np.stack(w.coef), (2, 9, 6, 12)))
+    for a in range(2):
+        for k in range(9):
+            i = a * 9 + k
+            Fo = dom.brdf(w.coef[i], w.tau[i], w.omega[i], 8, 12, 32)
+            assert np.abs(F[a][k].cpu().numpy() - Fo).max() < TOL * np.abs(Fo[..., 0, 0]).max(), (a, k)

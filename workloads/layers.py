@@ -277,12 +277,45 @@ def _large_c5() -> LayerSet:
                     [128], [256], [256], [256], [draws])
 
 
+SPECTRAL_WAVELENGTHS_NM = (400.0, 437.5, 475.0, 512.5, 550.0, 587.5, 625.0, 662.5, 700.0)
+
+
+def _spectral(n_materials: int = 8, N: int = 32, L: int = 64) -> LayerSet:
+    """Spectral batching: each material seen at nine wavelengths across the visible range (a
+    rendering needs one BRDF per wavelength), all (material, wavelength) layers in one batch,
+    material-major. Per material (seed 6, one substream each): a coefficient set from the HG-like
+    generator with asymmetry g, an optical thickness tau_550 and an albedo; across wavelengths
+    tau scales as (550 / lambda)^a (a ~ U[0.5, 2]), the co-albedo 1 - omega as (lambda / 550)^b
+    (b ~ U[-1, 1]), and the Legendre degree l of every family is damped by (550 / lambda)^(0.1 l)
+    relative to the material's set (the phase function loses forward peak towards the red). A
+    damped set that fails the validity inequalities keeps the material's set. N, L, M = L and
+    n_dphi = 32 are shared by all layers."""
+    taus, omegas, coefs, draws = [], [], [], []
+    for rng in _streams(6, n_materials):
+        base, _, d = hg_like_coefficients(rng, L)
+        tau550 = 10.0 ** rng.uniform(-0.5, 1.5)
+        om550 = rng.uniform(0.8, 0.995)
+        a, b = rng.uniform(0.5, 2.0), rng.uniform(-1.0, 1.0)
+        for lam in SPECTRAL_WAVELENGTHS_NM:
+            r = 550.0 / lam
+            c = base * (r ** (0.1 * np.arange(L)))[None, :]
+            c[0, 0] = 1.0
+            coefs.append(c if positivity_ok(c) else base.copy())
+            taus.append(tau550 * r ** a)
+            omegas.append(min(1.0 - (1.0 - om550) * (lam / 550.0) ** b, 0.999))
+            draws.append(d)
+    n = len(taus)
+    return LayerSet(f"spectral_{n_materials}x{len(SPECTRAL_WAVELENGTHS_NM)}", np.array(taus), np.array(omegas), coefs,
+                    [N] * n, [L] * n, [L] * n, [32] * n, draws)
+
+
 WORKLOADS = {
     "rayleigh": _rayleigh_c1,
     "particulate": _particulate_c2,
     "batched": _batched_c3,
     "differentiation": _differentiation_c4,
     "large": _large_c5,
+    "spectral": _spectral,
 }
 
 
