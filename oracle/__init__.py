@@ -20,6 +20,8 @@ Modules:
   phase       scattering matrix from coefficients, geometric phase matrix, its Fourier projection
   dom         per-order operator, eigen solution, boundary solve, synthesis of F_r
   particular  off-node incidence through the particular solution (eq. 28-33)
-  brute       matrix-exponential propagator solve at extended precision (tiny N)
+  stack       layer stacks (interface continuity, Sec. 2.C) and reflecting bases (eq. 57-66)
+  brute       matrix-exponential propagator solve at extended precision (tiny N), also for stacks
+              and bases (product of the layers' propagators)
   analytic    single-scattering limit and Chandrasekhar's H-function (isotropic scattering)
 """

@@ -75,3 +75,34 @@ def beam_response(coef, omega, tau0, m, N, mu0, dps=40):
             for a in range(n):
                 out[a, p] = float(x[a])
     return out
+
+
+def stack_stream_response(layers, m, N, Xb=None, dps=40):
+    """R^m at the top of a stack (stream form) through the product of the layers' propagators.
+
+    layers: [(coef, omega, tau0), ...] from the top down. Xb: the base as a matrix on the downward
+    radiance at the base (upward = Xb downward), or None for a black base. With
+    Psi = expm(K_last tau_last) ... expm(K_first tau_first) the field at the base is Psi times the
+    field at the top, so with the downward field at the top given the base condition reads
+    (Psi_{--} - Xb Psi_{+-}) I-(0) = (Xb Psi_{++} - Psi_{-+}) I+(0).
+    """
+    mu, alpha = double_gauss(N)
+    n = 4 * N
+    with mp.workdps(dps):
+        Psi = mp.eye(2 * n)
+        for coef, omega, tau0 in layers:
+            K, _, _ = _operator_mp(coef, omega, m, mu, alpha)
+            Psi = mp.expm(K * mp.mpf(tau0)) * Psi
+        X = mp.zeros(n, n)
+        if Xb is not None:
+            for a in range(n):
+                for b in range(n):
+                    X[a, b] = mp.mpf(float(Xb[a, b]))
+        Ppp, Ppm = Psi[:n, :n], Psi[:n, n:]
+        Pmp, Pmm = Psi[n:, :n], Psi[n:, n:]
+        Rop = mp.inverse(Pmm - X * Ppm) * (X * Ppp - Pmp)
+        out = np.zeros((n, n))
+        for a in range(n):
+            for b in range(n):
+                out[a, b] = float(Rop[a, b] / (mp.pi * mp.mpf(alpha[b // 4])))
+    return out
