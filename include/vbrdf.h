@@ -23,6 +23,10 @@
  *     reflection towards (-mu_i, phi). F_r is referred to the horizontal irradiance mu_q I0.
  *   - F_r layout per layer: [N_out = i][N_in = q][n_dphi = k][4 = r][4 = p], Stokes (I,Q,U,V).
  *     Layers are packed back to back in the order of the plan.
+ *   - Stacks and bases: by default every layer lies alone over a black base. A plan may instead
+ *     put layers on top of one another (vbrdf_plan_desc.below) and give the bottom of each stack
+ *     a reflecting base (vbrdf_plan_desc.base); a layer's F_r is then the BRDF of its sub-stack,
+ *     from that layer down to the base.
  *
  * Memory ownership: every pointer passed to these functions stays owned by the caller. Device
  * pointers must stay valid until the enqueued work on the given stream has completed. The plan
@@ -41,7 +45,7 @@
 extern "C" {
 #endif
 
-#define VBRDF_ABI_VERSION 2
+#define VBRDF_ABI_VERSION 3
 
 typedef int32_t vbrdf_status;
 #define VBRDF_OK 0
@@ -74,6 +78,19 @@ typedef int32_t vbrdf_status;
  * redoing its boundary solve in FP64. */
 #define VBRDF_FLAG_DISABLE_FP64_FALLBACK 16
 
+/* Reflecting base under the bottom layer of every stack (Sec. 2.C, base condition; Sec. 3.C,
+ * "Base Reflection", eq. 57-66). The base data are passed to vbrdf_solve_base. */
+#define VBRDF_BASE_BLACK 0      /* nothing is reflected (no base data) */
+#define VBRDF_BASE_LAMBERTIAN 1 /* ideal depolarising Lambertian base of albedo rho (R_00 = 2 rho,
+                                   eq. 66): one double per layer, read for bottom layers only */
+#define VBRDF_BASE_MUELLER 2    /* general per-order Mueller base: for every bottom layer (in plan
+                                   order) M blocks of (4N)^2 doubles, Rb^m[(i,r)][(j,p)] = Stokes r of
+                                   the upward radiance on node i per unit Stokes p of the downward
+                                   radiance on node j in order m, in the per-order representation of
+                                   the phase matrix (cos part on the IQ-IQ and UV-UV blocks, sin part
+                                   on the cross blocks); the base condition is
+                                   I_up(i) = sum_j alpha_j mu_j Rb^m(i, j) I_down(j) (eq. 58). */
+
 /* Largest supported quadrature order per hemisphere (Stokes system size 4N = 512). */
 #define VBRDF_MAX_N 128
 
@@ -101,6 +118,16 @@ typedef struct vbrdf_plan_desc {
    * default (2), -1 = none (the unrefined FP32 solve then fails the convergence test: for tests of
    * the fallback and of NONCONVERGED). Must be 0 for FP64. */
   int32_t refine_steps;
+  /* Layer stacks (Sec. 2.C: one homogeneous solution per layer, radiance continuous across each
+   * interface). NULL = every layer alone. Otherwise host [n_layers]: below[l] is the index of the
+   * layer directly beneath layer l, or -1 when layer l is the bottom of its stack. Each layer lies
+   * on at most one other, chains end (no cycles), at most 64 layers per stack, and the layers of a
+   * stack share N and M. Layer l's F_r is the BRDF of the stack from l down to the base. */
+  const int32_t* below;
+  /* VBRDF_BASE_* under the bottom layer of every stack (also for a layer alone). Plans with stacks
+   * or a non-black base accept neither VBRDF_FLAG_SAVE_FOR_BACKWARD nor
+   * VBRDF_FLAG_EMIT_TRANSMISSION. */
+  int32_t base;
 } vbrdf_plan_desc;
 
 /* ABI version of the loaded library (VBRDF_ABI_VERSION). */
@@ -152,6 +179,26 @@ size_t vbrdf_plan_workspace_bytes(const vbrdf_plan* plan);
  * boundary solve failed); such a layer's F_r is filled with NaN. */
 vbrdf_status vbrdf_solve(vbrdf_plan* plan, const double* tau, const double* omega, const double* coef,
                          double* F_r, int32_t* layer_status, void* stream);
+
+/* vbrdf_solve for plans with stacks or a reflecting base. Every layer is first solved over a black
+ * base as above; the stacks are then combined per order from the bottom up: with R~, T~ a layer's
+ * reflection and transmission operators on radiance at the nodes (upward fields stored mirrored,
+ * Stokes U and V negated) and X~ the reflection of what lies beneath it (the sub-stack, or the base
+ * as the matrix of eq. 58 in the same storage),
+ *     R~_stack = R~ + T~ (I - X~ R~)^-1 (X~ T~),
+ * which is the solution of the full boundary system with interface continuity and the base
+ * condition (the two agree exactly; the combined system is never formed).
+ *   base      device doubles as described for the plan's VBRDF_BASE_* (NULL for a black base):
+ *             LAMBERTIAN: rho[n_layers], 0 <= rho <= 1; MUELLER: vbrdf_plan_base_bytes() bytes
+ * Other arguments and the per-layer status as for vbrdf_solve. A layer whose sub-stack contains a
+ * failed layer gets that layer's status; an invalid rho or a non-finite Mueller entry gives INVALID
+ * for the stack's bottom layer (and so for the layers above it); a singular adding system gives
+ * NUMERIC. Errors: INVALID (null pointers; base NULL for a non-black base), as vbrdf_solve. */
+vbrdf_status vbrdf_solve_base(vbrdf_plan* plan, const double* tau, const double* omega, const double* coef,
+                              const double* base, double* F_r, int32_t* layer_status, void* stream);
+
+/* Bytes of base data vbrdf_solve_base reads for this plan (0 for a black base). */
+size_t vbrdf_plan_base_bytes(const vbrdf_plan* plan);
 
 /* Inspection of the last solve's per-order intermediates for one (layer, order), copied
  * synchronously (after waiting for `stream`) into caller-owned host arrays:

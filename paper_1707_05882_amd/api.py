@@ -43,10 +43,14 @@ class BRDFSolver:
         c = torch.as_tensor(pack_coefficients(coefs), device=dev)
         return t, w, c
 
-    def solve_device(self, tau_d, omega_d, coef_d, stream=None):
-        """Enqueue on `stream` (default: torch's current stream) with device-resident inputs."""
+    def solve_device(self, tau_d, omega_d, coef_d, stream=None, base_d=None):
+        """Enqueue on `stream` (default: torch's current stream) with device-resident inputs
+        (base_d: the base data of a plan with a reflecting base)."""
         s = torch.cuda.current_stream(self.device) if stream is None else stream
-        self.plan.solve(tau_d, omega_d, coef_d, self.F, self.status, s.cuda_stream)
+        if self.plan.below is None and self.plan.base == binding.BASE_BLACK:
+            self.plan.solve(tau_d, omega_d, coef_d, self.F, self.status, s.cuda_stream)
+        else:
+            self.plan.solve_base(tau_d, omega_d, coef_d, base_d, self.F, self.status, s.cuda_stream)
 
     def check(self):
         st = self.status.cpu().numpy()
@@ -54,9 +58,11 @@ class BRDFSolver:
         if len(bad):
             raise binding.VbrdfError(int(st[bad[0]]), f"layer(s) {bad.tolist()} failed with status {st[bad].tolist()}")
 
-    def __call__(self, tau, omega, coefs):
+    def __call__(self, tau, omega, coefs, base=None):
         t, w, c = self.upload(tau, omega, coefs)
-        self.solve_device(t, w, c)
+        b = None if base is None else torch.as_tensor(np.ascontiguousarray(base, dtype=np.float64).ravel(),
+                                                      device=self.device)
+        self.solve_device(t, w, c, base_d=b)
         torch.cuda.synchronize(self.device)
         self.check()
         return self._views
@@ -147,6 +153,28 @@ class SpectralBRDF:
 
 
 _PRECISIONS = {"fp64": binding.PRECISION_FP64, "fp32_refined": binding.PRECISION_FP32_REFINED}
+_BASES = {"black": binding.BASE_BLACK, "lambertian": binding.BASE_LAMBERTIAN, "mueller": binding.BASE_MUELLER}
+
+
+def stack_brdf(tau, omega, coef, N, M, n_dphi, base="black", rho=0.0, Rb=None, precision="fp64", device="cuda"):
+    """BRDF of a stack of layers (listed from the top down) over a base, on the Gauss-node grid.
+
+    tau, omega: sequences over the layers; coef: sequence of (6, L_l) arrays; every layer shares N,
+    M and n_dphi. base: "black", "lambertian" (albedo rho) or "mueller" (Rb: (M, 4N, 4N) per-order
+    base blocks Rb^m[(i, r), (j, p)], see VBRDF_BASE_MUELLER). Returns the (N, N, n_dphi, 4, 4) F_r
+    of the whole stack (the top layer's output).
+    """
+    nl = len(tau)
+    below = list(range(1, nl)) + [-1]
+    Ls = [np.asarray(c).shape[1] for c in coef]
+    s = BRDFSolver([N] * nl, Ls, [M] * nl, [n_dphi] * nl, device=device, precision=_PRECISIONS[precision],
+                   below=below, base=_BASES[base])
+    data = None
+    if base == "lambertian":
+        data = np.full(nl, float(rho))
+    elif base == "mueller":
+        data = np.asarray(Rb, dtype=np.float64)
+    return s(tau, omega, coef, base=data)[0].clone()
 
 
 def brdf(tau, omega, coef, N, M, n_dphi, precision="fp64", device="cuda"):

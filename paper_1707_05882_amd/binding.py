@@ -28,7 +28,10 @@ FLAG_GRAPH = 2
 FLAG_EMIT_TRANSMISSION = 4
 FLAG_SAVE_FOR_BACKWARD = 8
 FLAG_DISABLE_FP64_FALLBACK = 16
-ABI_VERSION = 2
+ABI_VERSION = 3
+BASE_BLACK = 0
+BASE_LAMBERTIAN = 1
+BASE_MUELLER = 2
 MAX_N = 128
 NOALLOC_SCRATCH_BYTES = 80 << 20
 
@@ -40,7 +43,7 @@ EXPORTED = (
     "vbrdf_workspace_query", "vbrdf_plan_destroy", "vbrdf_plan_output_bytes", "vbrdf_plan_workspace_bytes",
     "vbrdf_solve", "vbrdf_plan_inspect", "vbrdf_radiance", "vbrdf_plan_stage_times", "vbrdf_stage_name",
     "vbrdf_solve_noalloc", "vbrdf_backward", "vbrdf_plan_get_tuning", "vbrdf_plan_set_tuning",
-    "vbrdf_plan_autotune",
+    "vbrdf_plan_autotune", "vbrdf_solve_base", "vbrdf_plan_base_bytes",
 )
 EIGEN_PLAN_ORDER = 0
 EIGEN_LONGEST_FIRST = 1
@@ -72,6 +75,8 @@ class PlanDesc(ctypes.Structure):
         ("workspace_bytes", ctypes.c_uint64),
         ("qr_sweep_cap", ctypes.c_int32),
         ("refine_steps", ctypes.c_int32),
+        ("below", ctypes.POINTER(ctypes.c_int32)),
+        ("base", ctypes.c_int32),
     ]
 
 
@@ -123,6 +128,10 @@ def load():
     L.vbrdf_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.vbrdf_plan_autotune.restype = i32
     L.vbrdf_plan_autotune.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Tuning)]
+    L.vbrdf_solve_base.restype = i32
+    L.vbrdf_solve_base.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.vbrdf_plan_base_bytes.restype = ctypes.c_size_t
+    L.vbrdf_plan_base_bytes.argtypes = [vp]
     if L.vbrdf_abi_version() != ABI_VERSION:
         raise OSError("libvbrdf.so ABI version mismatch")
     _lib = L
@@ -175,7 +184,7 @@ class _Desc:
     """Keeps a PlanDesc and the shape arrays it points to alive together."""
 
     def __init__(self, N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes,
-                 qr_sweep_cap, refine_steps=0):
+                 qr_sweep_cap, refine_steps=0, below=None, base=BASE_BLACK):
         self.N, self.L, self.M, self.n_dphi = (_as_list(v) for v in (N, L, M, n_dphi))
         nl = len(self.N)
         if not (len(self.L) == len(self.M) == len(self.n_dphi) == nl):
@@ -183,14 +192,21 @@ class _Desc:
         arr = lambda v: (ctypes.c_int32 * nl)(*v)
         self.keep = [arr(self.N), arr(self.L), arr(self.M), arr(self.n_dphi)]
         ws = _ptr(workspace) if workspace is not None else None
-        self.desc = PlanDesc(ABI_VERSION, nl, *self.keep, int(precision), int(flags), int(workspace_cap_bytes),
-                             ws, int(workspace_bytes), int(qr_sweep_cap), int(refine_steps))
+        bl = None
+        if below is not None:
+            below = [int(b) for b in below]
+            if len(below) != nl:
+                raise ValueError("below needs one entry per layer")
+            bl = arr(below)
+            self.keep.append(bl)
+        self.desc = PlanDesc(ABI_VERSION, nl, *self.keep[:4], int(precision), int(flags), int(workspace_cap_bytes),
+                             ws, int(workspace_bytes), int(qr_sweep_cap), int(refine_steps), bl, int(base))
         self.n_layers = nl
 
 
-def workspace_query(N, L, M, n_dphi, precision=PRECISION_FP64, flags=0):
+def workspace_query(N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, below=None, base=BASE_BLACK):
     """Bytes of device workspace a plan of these shapes needs (host call)."""
-    d = _Desc(N, L, M, n_dphi, precision, flags, 0, None, 0, 0)
+    d = _Desc(N, L, M, n_dphi, precision, flags, 0, None, 0, 0, 0, below, base)
     out = ctypes.c_uint64()
     _check(load().vbrdf_workspace_query(ctypes.byref(d.desc), ctypes.byref(out)))
     return int(out.value)
@@ -200,9 +216,11 @@ class Plan:
     """Owns a vbrdf_plan. Shapes are per-layer lists (or scalars for one layer)."""
 
     def __init__(self, N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, workspace_cap_bytes=0,
-                 workspace=None, workspace_bytes=0, qr_sweep_cap=0, refine_steps=0):
+                 workspace=None, workspace_bytes=0, qr_sweep_cap=0, refine_steps=0, below=None, base=BASE_BLACK):
         d = _Desc(N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes, qr_sweep_cap,
-                  refine_steps)
+                  refine_steps, below, base)
+        self.below = None if below is None else [int(b) for b in below]
+        self.base = int(base)
         self.N, self.L, self.M, self.n_dphi = d.N, d.L, d.M, d.n_dphi
         self.flags = int(flags)
         self.precision = int(precision)
@@ -228,6 +246,14 @@ class Plan:
     def solve(self, tau, omega, coef, F_r, layer_status, stream=0):
         _check(load().vbrdf_solve(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(F_r), _ptr(layer_status),
                                   ctypes.c_void_p(int(stream))))
+
+    def solve_base(self, tau, omega, coef, base, F_r, layer_status, stream=0):
+        """vbrdf_solve_base: stacks and reflecting bases (base: device doubles, or None if black)."""
+        _check(load().vbrdf_solve_base(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(base), _ptr(F_r),
+                                       _ptr(layer_status), ctypes.c_void_p(int(stream))))
+
+    def base_bytes(self):
+        return load().vbrdf_plan_base_bytes(self._h)
 
     def get_tuning(self):
         t = Tuning()

@@ -24,7 +24,7 @@ constexpr int kNumStages = kNumSolveStages;
 constexpr int kTimedSolves = 256;  // solves whose stage events are kept between queries
 const char* const kStageNames[kNumStages] = {"validate", "legendre", "assemble", "gemm_FE", "eigen",  "gemm_U",
                                              "hqapply",  "refine",   "gemm_V",   "vfix",    "colscal", "bcbuild",
-                                             "lu",       "trsm",     "response", "synth"};
+                                             "lu",       "trsm",     "response", "stack",   "synth"};
 
 thread_local std::string g_err;
 
@@ -122,7 +122,8 @@ struct vbrdf_plan : LaunchSet {
   bool timing = false;
   bool graph = false;             // capture the solve into a hipGraph and replay it
   hipGraphExec_t gexec = nullptr;  // instantiated for the pointers in gkey
-  const void* gkey[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void* gkey[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t base_doubles = 0;  // base data a solve reads (vbrdf_plan_base_bytes / 8)
   int timed = 0;  // solves recorded since the last stage_times query (capped at kTimedSolves)
   std::vector<hipEvent_t> ev;  // kTimedSolves sets of kNumStages + 1 events
 
@@ -138,6 +139,10 @@ struct vbrdf_plan : LaunchSet {
     if (status_d) (void)hipFree(status_d);
     if (order_d) (void)hipFree(const_cast<int32_t*>(order_d));
     if (queue_d) (void)hipFree(queue_d);
+    if (below_d) (void)hipFree(const_cast<int32_t*>(below_d));
+    if (base_off_d) (void)hipFree(const_cast<int64_t*>(base_off_d));
+    if (stack_items_d) (void)hipFree(const_cast<Item*>(stack_items_d));
+    if (stack_tasks_d) (void)hipFree(const_cast<StackTask*>(stack_tasks_d));
   }
 };
 
@@ -198,7 +203,110 @@ static vbrdf_status check_desc(const vbrdf_plan_desc* d) {
     if (M > kSynthMaxM) return fail(VBRDF_E_UNSUPPORTED, "layer %d: M = %d above %d", l, M, kSynthMaxM);
     if (P > kSynthMaxPhi) return fail(VBRDF_E_UNSUPPORTED, "layer %d: n_dphi = %d above %d", l, P, kSynthMaxPhi);
   }
+  if (d->base != VBRDF_BASE_BLACK && d->base != VBRDF_BASE_LAMBERTIAN && d->base != VBRDF_BASE_MUELLER)
+    return fail(VBRDF_E_UNSUPPORTED, "unknown base kind %d", d->base);
+  bool stacks = false;
+  if (d->below) {
+    std::vector<int> above(d->n_layers, -1);
+    for (int l = 0; l < d->n_layers; ++l) {
+      const int b = d->below[l];
+      if (b == -1) continue;
+      if (b < 0 || b >= d->n_layers || b == l) return fail(VBRDF_E_INVALID, "layer %d: below = %d out of range", l, b);
+      if (above[b] >= 0) return fail(VBRDF_E_INVALID, "layers %d and %d both lie on layer %d", above[b], l, b);
+      above[b] = l;
+      if (d->N[b] != d->N[l] || d->M[b] != d->M[l])
+        return fail(VBRDF_E_INVALID, "layers %d and %d of one stack differ in N or M", l, b);
+      stacks = true;
+    }
+    for (int l = 0; l < d->n_layers; ++l) {  // every chain must end within kMaxStackLevels layers
+      int j = l, depth = 0;
+      while (d->below[j] >= 0 && depth <= d->n_layers) {
+        j = d->below[j];
+        ++depth;
+      }
+      if (d->below[j] >= 0) return fail(VBRDF_E_INVALID, "the stack under layer %d has a cycle", l);
+      if (depth >= kMaxStackLevels)
+        return fail(VBRDF_E_UNSUPPORTED, "the stack under layer %d is deeper than %d layers", l, kMaxStackLevels);
+    }
+  }
+  if ((stacks || d->base != VBRDF_BASE_BLACK) &&
+      (d->flags & (VBRDF_FLAG_SAVE_FOR_BACKWARD | VBRDF_FLAG_EMIT_TRANSMISSION)))
+    return fail(VBRDF_E_UNSUPPORTED, "stacks and reflecting bases take neither SAVE_FOR_BACKWARD nor EMIT_TRANSMISSION");
   return VBRDF_OK;
+}
+
+// Level tables of the stack stage. level(l) = 0 for the bottom layer of a stack, one more than the
+// layer beneath otherwise; level-0 items take an adding step only over a reflecting base.
+static vbrdf_status build_stacks(vbrdf_plan* p, const vbrdf_plan_desc* d) {
+  const int nl = d->n_layers;
+  std::vector<int32_t> below(nl, -1);
+  if (d->below)
+    for (int l = 0; l < nl; ++l) below[l] = d->below[l];
+  std::vector<int> level(nl, 0);
+  for (int l = 0; l < nl; ++l) {
+    int j = l, k = 0;
+    while (below[j] >= 0) {
+      j = below[j];
+      ++k;
+    }
+    level[l] = k;
+  }
+  std::vector<int64_t> base_off(nl, -1);
+  int64_t off = 0;
+  for (int l = 0; l < nl; ++l) {
+    if (below[l] >= 0) continue;
+    const Layer& ly = p->layers_h[l];
+    if (d->base == VBRDF_BASE_LAMBERTIAN) base_off[l] = l;
+    if (d->base == VBRDF_BASE_MUELLER) {
+      base_off[l] = off;
+      off += (int64_t)ly.M * 16 * ly.N * ly.N;
+    }
+  }
+  p->base_doubles = d->base == VBRDF_BASE_LAMBERTIAN ? (size_t)nl : (size_t)off;
+  std::vector<Item> sitems;
+  std::vector<StackTask> stasks;
+  int n_levels = 0;
+  for (int l = 0; l < nl; ++l) n_levels = std::max(n_levels, level[l] + 1);
+  p->n_levels = n_levels;
+  for (int k = 0; k < n_levels; ++k) {
+    p->lvl_off[k] = (int)sitems.size();
+    for (int l = 0; l < nl; ++l) {
+      if (level[l] != k) continue;
+      if (below[l] < 0 && d->base == VBRDF_BASE_BLACK) continue;  // nothing beneath to add
+      const Layer& ly = p->layers_h[l];
+      const int64_t nn = 16 * (int64_t)ly.N * ly.N;
+      for (int m = 0; m < ly.M; ++m) {
+        const Item& it = p->items_h[ly.item0 + m];
+        StackTask tk{};
+        if (below[l] >= 0) {
+          tk.src_ws = p->items_h[p->layers_h[below[l]].item0 + m].ws;
+          tk.src_layer = below[l];
+          tk.base_off = -1;
+        } else {
+          tk.src_ws = -1;
+          tk.src_layer = -1;
+          tk.base_off = d->base == VBRDF_BASE_MUELLER ? base_off[l] + m * nn : base_off[l];
+        }
+        sitems.push_back(it);
+        stasks.push_back(tk);
+      }
+    }
+  }
+  p->lvl_off[n_levels] = (int)sitems.size();
+  p->stacked = true;
+  int32_t* below_d = nullptr;
+  int64_t* base_off_d = nullptr;
+  Item* sitems_d = nullptr;
+  StackTask* stasks_d = nullptr;
+  vbrdf_status st = upload(below, &below_d);
+  p->below_d = below_d;
+  if (st == VBRDF_OK) st = upload(base_off, &base_off_d);
+  p->base_off_d = base_off_d;
+  if (st == VBRDF_OK) st = upload(sitems, &sitems_d);
+  p->stack_items_d = sitems_d;
+  if (st == VBRDF_OK) st = upload(stasks, &stasks_d);
+  p->stack_tasks_d = stasks_d;
+  return st;
 }
 
 // Per-item workspace blocks, 256-byte aligned.
@@ -370,6 +478,14 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       return fail(VBRDF_E_NOMEM, "workspace allocation of %zu bytes failed: %s", need, hipGetErrorString(e));
     }
   }
+  p->base_kind = d->base;
+  if (d->below || d->base != VBRDF_BASE_BLACK) {
+    const vbrdf_status sst = build_stacks(p, d);
+    if (sst != VBRDF_OK) {
+      delete p;
+      return sst;
+    }
+  }
   *out = p;
   return VBRDF_OK;
 }
@@ -387,10 +503,12 @@ size_t vbrdf_plan_workspace_bytes(const vbrdf_plan* plan) { return plan ? plan->
 
 namespace vbrdf {
 
+static void enqueue_stacks(const LaunchSet& ls, const double* base, int32_t* layer_status, hipStream_t s);
+
 // The launch sequence of one solve on stream s; when evs is given, kNumSolveStages + 1 events are
 // recorded around and between the stages.
-void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef, double* F_r,
-                   int32_t* layer_status, hipStream_t s, hipEvent_t* evs) {
+void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef,
+                   const double* base, double* F_r, int32_t* layer_status, hipStream_t s, hipEvent_t* evs) {
   const LaunchSet* p = &ls;
   const int ni = p->n_items, mn = p->max_n, mN = p->max_N;
   int stage = 0;
@@ -484,12 +602,44 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
     launch_trsm(p->trsm_rows, xg, p->trsm_lds, s, p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, trb);
     mark();
   }
+  const int rmode = p->stacked ? kResponseBrackets : (p->transmission ? kResponseTransmission : 0);
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status,
-                                                       p->transmission ? 1 : 0);
+                                                       rmode);
+  mark();
+  if (p->stacked) enqueue_stacks(*p, base, layer_status, s);
   mark();
   k_synth<<<p->n_tasks, 256, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
   if (p->save) k_copy_status<<<(p->n_layers + 255) / 256, 256, 0, s>>>(layer_status, p->status_d, p->n_layers);
   mark();
+}
+
+// The stack stage: base checks, status inheritance, then one adding step per level from the bottom
+// up (formulas in k_stack.hip), and the final scaling of every item's response.
+static void enqueue_stacks(const LaunchSet& ls, const double* base, int32_t* layer_status, hipStream_t s) {
+  const LaunchSet* p = &ls;
+  const int mn = p->max_n, gt = (mn + 63) / 64, et = (mn + 15) / 16;
+  if (p->base_kind != VBRDF_BASE_BLACK)
+    k_stack_validate<<<p->n_layers, 256, 0, s>>>(p->layers_d, p->below_d, p->base_kind, base, p->base_off_d,
+                                                  layer_status);
+  k_stack_status<<<(p->n_layers + 255) / 256, 256, 0, s>>>(p->n_layers, p->below_d, layer_status);
+  const int xb = std::min(1024, (mn * mn + 255) / 256);
+  for (int k = 0; k < p->n_levels; ++k) {
+    const int cnt = p->lvl_off[k + 1] - p->lvl_off[k];
+    if (cnt == 0) continue;
+    const Item* it = p->stack_items_d + p->lvl_off[k];
+    const StackTask* tk = p->stack_tasks_d + p->lvl_off[k];
+    k_stack_x<<<dim3(xb, cnt), 256, 0, s>>>(it, tk, p->layers_d, p->quad_d, p->base_kind, base, p->ws_d,
+                                            layer_status);
+    const dim3 gg(gt, gt, cnt);
+    k_gemm<<<gg, 256, 0, s>>>(it, p->ws_d, kBufG, kBufE, kBufZ, kGemmNegate | kGemmAccumulate, layer_status);  // I - X R
+    k_gemm<<<gg, 256, 0, s>>>(it, p->ws_d, kBufG, kBufF, kBufYS, 0, layer_status);                             // X T
+    k_lu<<<dim3(cnt, 1), 1024, 0, s>>>(it, p->ws_d, layer_status, LuBufs{{kBufZ, kBufZ}, {kBufX, kBufX}, 0});
+    launch_trsm(p->trsm_rows, dim3(xcd_grid(cnt, p->trsm_tiles)), p->trsm_lds, s, it, cnt, p->trsm_tiles, p->ws_d,
+                layer_status, TrsmBufs{{kBufX, kBufX}, {kBufF, kBufF}, {kBufU, kBufU}, 1, 0});  // T (I - X R)^-1
+    k_gemm<<<gg, 256, 0, s>>>(it, p->ws_d, kBufU, kBufYS, kBufE, kGemmAccumulate, layer_status);  // R += Y (X T)
+  }
+  k_stack_finish<<<dim3(et, et, p->n_items), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d,
+                                                                    layer_status);
 }
 
 // The adjoint sequence over all items (see k_adjoint.hip for the formulas and buffer roles).
@@ -540,23 +690,21 @@ void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omeg
 
 extern "C" {
 
-vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, const double* coef, double* F_r,
-                         int32_t* layer_status, void* stream) {
-  if (!p) return fail(VBRDF_E_INVALID, "null plan");
-  if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
+static vbrdf_status solve_impl(vbrdf_plan* p, const double* tau, const double* omega, const double* coef,
+                               const double* base, double* F_r, int32_t* layer_status, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (p->graph) {
     if (!s) return fail(VBRDF_E_INVALID, "graph replay needs a non-default stream");
-    const void* key[6] = {tau, omega, coef, F_r, layer_status, stream};
+    const void* key[7] = {tau, omega, coef, F_r, layer_status, stream, base};
     bool same = p->gexec != nullptr;
-    for (int i = 0; i < 6; ++i) same = same && key[i] == p->gkey[i];
+    for (int i = 0; i < 7; ++i) same = same && key[i] == p->gkey[i];
     if (!same) {
       if (p->gexec) {
         HIP_TRY(hipGraphExecDestroy(p->gexec));
         p->gexec = nullptr;
       }
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s, nullptr);
+      enqueue_solve(*p, tau, omega, coef, base, F_r, layer_status, s, nullptr);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(s, &g);
       if (ec != hipSuccess) return fail(VBRDF_E_DEVICE, "stream capture: %s", hipGetErrorString(ec));
@@ -566,7 +714,7 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
         p->gexec = nullptr;
         return fail(VBRDF_E_DEVICE, "graph instantiation: %s", hipGetErrorString(ei));
       }
-      for (int i = 0; i < 6; ++i) p->gkey[i] = key[i];
+      for (int i = 0; i < 7; ++i) p->gkey[i] = key[i];
     }
     HIP_TRY(hipGraphLaunch(p->gexec, s));
     p->solved = true;
@@ -574,12 +722,32 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
   }
   const bool rec = p->timing && p->timed < kTimedSolves;
   p->solved = true;
-  enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s,
+  enqueue_solve(*p, tau, omega, coef, base, F_r, layer_status, s,
                 rec ? &p->ev[(size_t)p->timed * (kNumStages + 1)] : nullptr);
   if (rec) ++p->timed;
   HIP_TRY(hipGetLastError());
   return VBRDF_OK;
 }
+
+vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, const double* coef, double* F_r,
+                         int32_t* layer_status, void* stream) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
+  if (p->base_kind != VBRDF_BASE_BLACK)
+    return fail(VBRDF_E_INVALID, "the plan has a reflecting base: its data go through vbrdf_solve_base");
+  return solve_impl(p, tau, omega, coef, nullptr, F_r, layer_status, stream);
+}
+
+vbrdf_status vbrdf_solve_base(vbrdf_plan* p, const double* tau, const double* omega, const double* coef,
+                              const double* base, double* F_r, int32_t* layer_status, void* stream) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
+  if (p->base_kind != VBRDF_BASE_BLACK && !base) return fail(VBRDF_E_INVALID, "null base data for a reflecting base");
+  return solve_impl(p, tau, omega, coef, p->base_kind == VBRDF_BASE_BLACK ? nullptr : base, F_r, layer_status,
+                    stream);
+}
+
+size_t vbrdf_plan_base_bytes(const vbrdf_plan* p) { return p ? p->base_doubles * sizeof(double) : 0; }
 
 vbrdf_status vbrdf_plan_inspect(const vbrdf_plan* p, int32_t layer, int32_t m, double* R_out, double* lam_re,
                                 double* lam_im, double* T_out, void* stream) {
@@ -648,6 +816,7 @@ vbrdf_status vbrdf_plan_autotune(vbrdf_plan* p, const double* tau, const double*
                                  double* F_r, int32_t* layer_status, void* stream, vbrdf_tuning* chosen) {
   if (!p) return fail(VBRDF_E_INVALID, "null plan");
   if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
+  if (p->base_kind != VBRDF_BASE_BLACK) return fail(VBRDF_E_UNSUPPORTED, "autotune of a plan with a reflecting base");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   std::vector<hipEvent_t> ev(kNumSolveStages + 1, nullptr);
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
@@ -662,7 +831,7 @@ vbrdf_status vbrdf_plan_autotune(vbrdf_plan* p, const double* tau, const double*
     for (int c = 0; c < 3; ++c) {
       p->eigen_mode = cand_e[c];
       set_trsm_rows(p, cand_r[c]);
-      enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s, ev.data());
+      enqueue_solve(*p, tau, omega, coef, nullptr, F_r, layer_status, s, ev.data());
       hipError_t e = hipEventSynchronize(ev[kNumSolveStages]);
       float te = 0.0f, tr = 0.0f;
       if (e == hipSuccess) e = hipEventElapsedTime(&te, ev[eig_stage], ev[eig_stage + 1]);
@@ -685,7 +854,7 @@ vbrdf_status vbrdf_plan_autotune(vbrdf_plan* p, const double* tau, const double*
   p->eigen_mode = pick_e;
   set_trsm_rows(p, pick_r);
   if (st == VBRDF_OK) {  // leave the result of the chosen configuration behind
-    enqueue_solve(*p, tau, omega, coef, F_r, layer_status, s, nullptr);
+    enqueue_solve(*p, tau, omega, coef, nullptr, F_r, layer_status, s, nullptr);
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = fail(VBRDF_E_DEVICE, "autotune: %s", hipGetErrorString(e));
   }

@@ -588,7 +588,7 @@ __global__ __launch_bounds__(256) void k_vfix(const Item* items, double* ws, int
 // field at the base for the same inputs, T^m = (Y_S - Y_T) R0 (the attenuated incident stream
 // included: in the stream form the total field is what the boundary solve returns), over kBufF.
 __global__ void k_response(const Item* items, const Layer* layers, const double* quad, double* ws,
-                           const int32_t* status, int transmission) {
+                           const int32_t* status, int mode) {
   const Item it = items[blockIdx.z];
   if (status[it.layer] != 0) return;
   const int n = it.n;
@@ -600,11 +600,16 @@ __global__ void k_response(const Item* items, const Layer* layers, const double*
   const int64_t idx = (int64_t)a * n + b;
   const double ys = base[(int64_t)kBufYS * n * n + idx], yt = base[(int64_t)kBufYT * n * n + idx];
   const double y = ys + yt - (a == b ? 1.0 : 0.0);
+  if (mode & kResponseBrackets) {
+    base[(int64_t)kBufE * n * n + idx] = y;
+    base[(int64_t)kBufF * n * n + idx] = ys - yt;
+    return;
+  }
   const double alq = quad[ly.quad_off + it.N + b / 4];
   const double sgn = ((a & 3) >= 2) ? -1.0 : 1.0;
   const double r0 = 1.0 / (3.141592653589793 * alq);
   base[(int64_t)kBufE * n * n + idx] = sgn * y * r0;
-  if (transmission) base[(int64_t)kBufF * n * n + idx] = (ys - yt) * r0;
+  if (mode & kResponseTransmission) base[(int64_t)kBufF * n * n + idx] = (ys - yt) * r0;
 }
 
 // ---- FP32-refined boundary solve -------------------------------------------------------------

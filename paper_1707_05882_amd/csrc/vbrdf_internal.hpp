@@ -188,9 +188,30 @@ __host__ __device__ inline void xcd_split(int id, int tiles, int& group, int& ti
   tile = rem / kXcds;
   group = blk * kXcds + rem % kXcds;
 }
-// R^m into kBufE; with transmission also T^m = (U S'^-1 - U T'^-1) R0 into kBufF
+// R^m into kBufE; with transmission also T^m = (U S'^-1 - U T'^-1) R0 into kBufF. mode
+// kResponseBrackets instead writes the unscaled operators R~ = U S'^-1 + U T'^-1 - I (kBufE) and
+// T~ = U S'^-1 - U T'^-1 (kBufF) for the stack stage.
+constexpr int kResponseTransmission = 1, kResponseBrackets = 2;
 __global__ void k_response(const Item* items, const Layer* layers, const double* quad, double* ws,
-                           const int32_t* status, int transmission);
+                           const int32_t* status, int mode);
+// ---- layer stacks and reflecting bases (k_stack.hip)
+// One adding step per item of a level: the reflection beneath comes from the item below (its
+// combined R~ in kBufE, at workspace offset src_ws) or, for src_ws < 0, from the base data at
+// base_off (Lambertian: the layer's rho; Mueller: this order's block).
+struct StackTask {
+  int64_t src_ws;
+  int64_t base_off;
+  int32_t src_layer;  // the layer beneath (its status is inherited), or -1
+  int32_t pad;
+};
+constexpr int kMaxStackLevels = 64;
+__global__ void k_stack_validate(const Layer* layers, const int32_t* below, int base_kind, const double* base,
+                                 const int64_t* base_off, int32_t* status);
+__global__ void k_stack_status(int n_layers, const int32_t* below, int32_t* status);
+__global__ void k_stack_x(const Item* items, const StackTask* tasks, const Layer* layers, const double* quad,
+                          int base_kind, const double* base, double* ws, int32_t* status);
+__global__ void k_stack_finish(const Item* items, const Layer* layers, const double* quad, double* ws,
+                               const int32_t* status);
 __global__ void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
                         const double* ws, double* F, const int32_t* status);
 // Device tables and launch shape of a solve: the plan's, or those of the allocation-free entry
@@ -218,6 +239,15 @@ struct LaunchSet {
   int refine_steps = 0;       // FP32-refined: correction steps of the boundary solve
   bool save = false;          // keep the state the adjoint needs (E~, F~ copies, layer status)
   int32_t* status_d = nullptr;  // copy of the last forward's layer status (adjoint plans)
+  // layer stacks and bases
+  bool stacked = false;                     // below[] given or a reflecting base
+  int base_kind = 0;                        // VBRDF_BASE_*
+  const int32_t* below_d = nullptr;         // per layer: the layer beneath, or -1
+  const int64_t* base_off_d = nullptr;      // per layer: offset of its base data (doubles)
+  const Item* stack_items_d = nullptr;      // items that take an adding step, grouped by level
+  const StackTask* stack_tasks_d = nullptr; // matching tasks
+  int n_levels = 0;
+  int lvl_off[kMaxStackLevels + 1] = {};    // level k: stack items [lvl_off[k], lvl_off[k + 1])
 };
 constexpr int kBoundaryRefineSteps = 2;  // FP32-refined boundary solve: correction steps
 
@@ -225,9 +255,9 @@ constexpr int kBoundaryRefineSteps = 2;  // FP32-refined boundary solve: correct
 int32_t vbrdf_fail(int32_t code, const char* fmt, ...);
 
 // Stages of the launch sequence (events are recorded around and between them when requested).
-constexpr int kNumSolveStages = 16;
-void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef, double* F_r,
-                   int32_t* layer_status, hipStream_t s, hipEvent_t* evs);
+constexpr int kNumSolveStages = 17;
+void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef,
+                   const double* base, double* F_r, int32_t* layer_status, hipStream_t s, hipEvent_t* evs);
 void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omega, const double* dF, double* dtau,
                       double* domega, double* dcoef, hipStream_t s);
 

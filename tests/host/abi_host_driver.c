@@ -75,12 +75,30 @@ int main(void) {
   bad = d;
   bad.M = Mbad;
   EXPECT(vbrdf_plan_create(&bad, &p) == VBRDF_E_INVALID);
+  int32_t below_bad[3] = {1, 2, 1}, below_ok[3] = {-1, -1, -1};
+  bad = d;
+  bad.below = below_bad;
+  EXPECT(vbrdf_plan_create(&bad, &p) == VBRDF_E_INVALID);
+  bad = d;
+  bad.below = below_ok;
+  bad.base = 7;
+  EXPECT(vbrdf_plan_create(&bad, &p) == VBRDF_E_UNSUPPORTED);
+  bad = d;
+  bad.below = below_ok;
+  bad.base = VBRDF_BASE_LAMBERTIAN;
+  bad.flags = VBRDF_FLAG_EMIT_TRANSMISSION;
+  EXPECT(vbrdf_plan_create(&bad, &p) == VBRDF_E_UNSUPPORTED);
+  bad.flags = 0;
+  uint64_t qb = 0;
+  EXPECT(vbrdf_workspace_query(&bad, &qb) == VBRDF_OK && qb == bytes);
   EXPECT(vbrdf_plan_create(NULL, &p) == VBRDF_E_INVALID);
   EXPECT(vbrdf_plan_create(&d, NULL) == VBRDF_E_INVALID);
 
   EXPECT(vbrdf_plan_destroy(NULL) == VBRDF_OK);
   EXPECT(vbrdf_plan_output_bytes(NULL) == 0 && vbrdf_plan_workspace_bytes(NULL) == 0);
   EXPECT(vbrdf_solve(NULL, NULL, NULL, NULL, NULL, NULL, NULL) == VBRDF_E_INVALID);
+  EXPECT(vbrdf_solve_base(NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == VBRDF_E_INVALID);
+  EXPECT(vbrdf_plan_base_bytes(NULL) == 0);
   EXPECT(vbrdf_backward(NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == VBRDF_E_INVALID);
   EXPECT(vbrdf_plan_inspect(NULL, 0, 0, NULL, NULL, NULL, NULL, NULL) == VBRDF_E_INVALID);
   double i0[4] = {1, 0, 0, 0};
@@ -92,7 +110,7 @@ int main(void) {
   EXPECT(vbrdf_plan_autotune(NULL, NULL, NULL, NULL, NULL, NULL, NULL, &t) == VBRDF_E_INVALID);
   for (int i = -2; i < 20; ++i) {
     const char* s = vbrdf_stage_name(i);
-    EXPECT((i >= 0 && i < 16) ? (s != NULL && strlen(s) > 0) : s == NULL);
+    EXPECT((i >= 0 && i < 17) ? (s != NULL && strlen(s) > 0) : s == NULL);
   }
   double* fake = (double*)0x100000;
   int32_t* ifake = (int32_t*)0x100000;

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert binding.abi_version() == binding.ABI_VERSION == 2
+    assert binding.abi_version() == binding.ABI_VERSION == 3
 
 
 @pytest.mark.parametrize("N", [1, 2, 3, 8, 32, 64, 128])
@@ -68,6 +68,19 @@ def test_gauss_nodes_rejects_bad_order():
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace_bytes=4096), binding.E_INVALID),  # bytes, no pointer
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace=0x100000, workspace_bytes=256), binding.E_NOMEM),
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], workspace_cap_bytes=1024), binding.E_NOMEM),
+    # stacks and bases
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], base=3), binding.E_UNSUPPORTED),  # unknown base kind
+    (dict(N=[8, 8], L=[4, 4], M=[2, 2], n_dphi=[8, 8], below=[2, -1]), binding.E_INVALID),  # out of range
+    (dict(N=[8, 8], L=[4, 4], M=[2, 2], n_dphi=[8, 8], below=[0, -1]), binding.E_INVALID),  # on itself
+    (dict(N=[8] * 3, L=[4] * 3, M=[2] * 3, n_dphi=[8] * 3, below=[2, 2, -1]), binding.E_INVALID),  # two on one
+    (dict(N=[8] * 3, L=[4] * 3, M=[2] * 3, n_dphi=[8] * 3, below=[1, 2, 1]), binding.E_INVALID),  # cycle
+    (dict(N=[8, 6], L=[4, 4], M=[2, 2], n_dphi=[8, 8], below=[1, -1]), binding.E_INVALID),  # N differs
+    (dict(N=[8, 8], L=[4, 4], M=[2, 3], n_dphi=[8, 8], below=[1, -1]), binding.E_INVALID),  # M differs
+    (dict(N=[8, 8], L=[4, 4], M=[2, 2], n_dphi=[8, 8], below=[1, -1], flags=8), binding.E_UNSUPPORTED),
+    (dict(N=[8, 8], L=[4, 4], M=[2, 2], n_dphi=[8, 8], below=[1, -1], flags=4), binding.E_UNSUPPORTED),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], base=1, flags=8), binding.E_UNSUPPORTED),  # base + adjoint
+    (dict(N=[8] * 65, L=[4] * 65, M=[2] * 65, n_dphi=[8] * 65, below=list(range(1, 65)) + [-1]),
+     binding.E_UNSUPPORTED),  # deeper than 64 layers
 ])
 def test_plan_validation(kw, code):
     with pytest.raises(binding.VbrdfError) as e:
@@ -79,9 +92,14 @@ def test_plan_validation(kw, code):
 def test_null_plan_calls_are_rejected():
     lib = binding.load()
     assert lib.vbrdf_solve(None, None, None, None, None, None, None) == binding.E_INVALID
+    assert lib.vbrdf_solve_base(None, None, None, None, None, None, None, None) == binding.E_INVALID
+    assert lib.vbrdf_plan_base_bytes(None) == 0
     assert lib.vbrdf_plan_destroy(None) == binding.OK
     assert lib.vbrdf_plan_output_bytes(None) == 0
     assert lib.vbrdf_stage_name(0).decode() == "validate"
+    assert lib.vbrdf_stage_name(15).decode() == "stack"
+    assert lib.vbrdf_stage_name(16).decode() == "synth"
+    assert lib.vbrdf_stage_name(17) is None
     assert lib.vbrdf_stage_name(99) is None
 
 

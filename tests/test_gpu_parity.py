@@ -192,7 +192,7 @@ def test_stage_timing():
     plan.solve(t, w, c, F, st, torch.cuda.current_stream().cuda_stream)
     times = plan.stage_times()
     assert list(times) == ["validate", "legendre", "assemble", "gemm_FE", "eigen", "gemm_U", "hqapply", "refine", "gemm_V",
-                           "vfix", "colscal", "bcbuild", "lu", "trsm", "response", "synth"]
+                           "vfix", "colscal", "bcbuild", "lu", "trsm", "response", "stack", "synth"]
     assert all(v >= 0 for v in times.values())
 
 
