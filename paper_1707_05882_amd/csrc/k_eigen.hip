@@ -5,7 +5,8 @@
 // one workgroup solves one (layer, order) matrix and all orders of all layers run in one launch.
 //
 // Steps (all in FP64):
-//   1. Householder reduction to upper Hessenberg form, accumulating the orthogonal factor Z,
+//   1. Householder reduction to upper Hessenberg form (the Householder vectors are kept in the
+//      workspace; k_hqapply applies them later, so the orthogonal factor is not accumulated here),
 //   2. implicit double-shift (Francis) QR to real Schur form T = Z^T H Z with deflation by the
 //      Ahues-Tisseur criterion, exceptional shifts every 10 stagnant sweeps, a real shift pair
 //      replaced by the eigenvalue closer to the corner used twice, and after 40 stagnant sweeps
@@ -104,8 +105,8 @@ __device__ __forceinline__ void wave_sync() {
 enum : int { kActDeflated = 0, kActSweep = 1, kActRotate = 2, kActStop = 3, kActMulti = 4 };
 
 // Multi-bulge passes: with at least kMultiMin active rows and fewer than kMultiIts iterations since
-// the last deflation, one pass chases one bulge per wave (up to 4 double shifts at once), the
-// bulges kMultiGap rows apart. Otherwise a single double-shift sweep runs on wave 0.
+// the last deflation, one pass chases one bulge per wave (up to kMaxBulges = 8 double shifts at
+// once), the bulges kMultiGap rows apart. Otherwise a single double-shift sweep runs on wave 0.
 constexpr int kMultiMin = 32;
 constexpr int kMultiIts = 6;
 constexpr int kMultiGap = 4;
