@@ -408,6 +408,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     int32_t* order_d = nullptr;
     st = upload(order, &order_d);
     p->order_d = order_d;
+    for (const Item& it : p->items_h) p->n_big += it.n > kLdsMaxn ? 1 : 0;
   }
   if (st == VBRDF_OK) {
     std::vector<int32_t> zero(1, 0);
@@ -533,13 +534,21 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   const dim3 gg(gt, gt, ni);
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufE, kBufG, 0, layer_status);  // G = F~ E~
   mark();
+  // problems above the LDS size by their own kernel (the same for every schedule, so a schedule
+  // never changes a result), largest first; then the others in the chosen schedule
+  const int nb = p->n_big;
+  if (nb > 0)
+    k_eigen_big<<<nb, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, p->order_d);
   if (p->eigen_mode == kEigenPersistent && p->queue_d && p->order_d) {
-    k_reset_counter<<<1, 1, 0, s>>>(p->queue_d);
-    k_eigen_persistent<<<std::min(ni, p->persist_groups), kEigenThreads, 0, s>>>(
-        p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, p->order_d, p->queue_d, ni);
-  } else {
-    const int32_t* ord = p->eigen_mode == kEigenPlanOrder ? nullptr : p->order_d;
-    k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, ord);
+    if (ni > nb) {
+      k_reset_counter<<<1, 1, 0, s>>>(p->queue_d);
+      k_eigen_persistent<<<std::min(ni - nb, p->persist_groups), kEigenThreads, 0, s>>>(
+          p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, p->order_d + nb, p->queue_d, ni - nb);
+    }
+  } else if (p->eigen_mode == kEigenPlanOrder || !p->order_d) {
+    if (ni > nb) k_eigen<<<ni, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, nullptr);
+  } else if (ni > nb) {
+    k_eigen<<<ni - nb, kEigenThreads, 0, s>>>(p->items_d, p->ws_d, layer_status, p->qr_sweep_cap, p->order_d + nb);
   }
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, kBufX, kBufG, kGemmTransA, layer_status);  // U' = Z X

@@ -182,6 +182,235 @@ __device__ inline int hess_line(int tid, int P, int NT) {
   return 32 * (hw / P) + P * (l32 / P) + hw % P;
 }
 
+// ---- Windowed multi-bulge pass for systems kept in global memory (n > kLdsMaxn)
+//
+// Chasing the bulges through H in global memory costs, per chain step and bulge, a read and write
+// of three rows and three columns of H and three columns of Z: the whole matrix streams through
+// the caches once per few steps and, with one problem per compute unit, the L2 of an XCD cannot
+// hold the working sets. Here the pass works on a kWin x kWin diagonal window of H held in LDS:
+// the chain is chased inside the window (left updates limited to the window's columns, right
+// updates to its rows), the reflectors are accumulated into an orthogonal U (kWin x kWin, LDS),
+// and when the leading bulge reaches the window's end the parts outside the window take the
+// window's whole transformation at once on the matrix cores:
+//     H[a:b, b:n] <- U^T H[a:b, b:n],   H[0:a, a:b] <- H[0:a, a:b] U,   Z[:, a:b] <- Z[:, a:b] U.
+// The next window starts one row above the trailing bulge, so every bulge's reflector input stays
+// inside a window, and moves the chain kWin - 4 (bulges) rows further.
+constexpr int kWin = 88;          // window rows and columns
+constexpr int kWinLd = kWin + 1;  // LDS row stride of the window
+constexpr int kWinU = 96;         // LDS row stride of U: columns padded to whole 16-column MFMA tiles
+static_assert(kWin % 4 == 0 && kWinU % 16 == 0 && kWinU >= kWin, "MFMA tiling of the window update");
+static_assert(kWin * kWinLd + kWin * kWinU <= kLdsMaxn * (kLdsMaxn + 1) + 3 * 64,
+              "window and U fit the LDS buffer of the LDS-resident path");
+static_assert(kWin > 4 * kMaxBulges + 4, "a window holds the whole bulge chain and lets it advance");
+// Largest system that takes the windowed pass. Larger ones (n = 512) keep the pass that updates H
+// and Z in global memory step by step: at N = 128 one nearly degenerate node cluster's per-order
+// response depends on the rounding of the QR phase more than the eigenpair refinement can absorb
+// (a close pair whose second-order coupling to the node's other Stokes eigenvalues it neglects),
+// and that path is the one its per-order accuracy was established on.
+constexpr int kWinMaxN = 256;
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// Reflector (I - tau u u^T), u = (1, u1, u2), taking (x, y, z) to (beta, 0, 0),
+// beta = -sign(x) ||(x, y, z)||; the identity (tau = 0, beta = x) when y = z = 0.
+__device__ __forceinline__ void householder3(double x, double y, double z, double& tau, double& u1, double& u2,
+                                             double& beta) {
+  tau = 0.0;
+  u1 = 0.0;
+  u2 = 0.0;
+  beta = x;
+  if (y == 0.0 && z == 0.0) return;
+  double xs = x, ys = y, zs = z, unscale = 1.0;
+  double s2 = xs * xs + ys * ys + zs * zs;
+  if (s2 < 0x1p-900) {  // keep the squares clear of the subnormal range
+    xs *= 0x1p600;
+    ys *= 0x1p600;
+    zs *= 0x1p600;
+    unscale = 0x1p-600;
+    s2 = xs * xs + ys * ys + zs * zs;
+  }
+  double r = __builtin_amdgcn_rsq(s2);
+  const double h2 = 0.5 * s2;
+  r = r * fma(-h2 * r, r, 1.5);
+  r = r * fma(-h2 * r, r, 1.5);
+  const double nrm = s2 * r;
+  const double ax = fabs(xs);
+  tau = fma(ax, r, 1.0);
+  const double dd = ax + nrm;
+  double q = __builtin_amdgcn_rcp(dd);
+  q = fma(q, fma(-dd, q, 1.0), q);
+  q = fma(q, fma(-dd, q, 1.0), q);
+  const double sc = copysign(q, xs);
+  u1 = ys * sc;
+  u2 = zs * sc;
+  beta = -copysign(nrm, xs) * unscale;
+}
+
+// X <- X U for rows 16 rb .. 16 rb + 15 of an m x w block of global memory (X[r][j] at
+// X0[r sr + j sj]), U in LDS (U[k][j] at sU[k kWinU + j], zero outside w x w). One wave: the 16 rows
+// are loaded whole as the A operands of v_mfma_f64_16x16x4 (row = lane % 16, k = lane / 16 + 4 t)
+// before any of them is stored; B = U (k = lane / 16, column = lane % 16); the accumulator holds
+// row lane / 16 + 4 v, column lane % 16.
+__device__ __forceinline__ void window_update_rows(double* __restrict__ X0, int64_t sr, int64_t sj, int m, int w,
+                                                   const double* __restrict__ sU, int rb, int lane) {
+  constexpr int kT = kWin / 4;
+  const int lr = lane & 15, kq = lane >> 4;
+  const int r = rb * 16 + lr;
+  double a[kT];
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const int k = 4 * t + kq;
+    a[t] = (r < m && k < w) ? X0[(int64_t)r * sr + (int64_t)k * sj] : 0.0;
+  }
+#pragma unroll 1
+  for (int cb = 0; cb < kWinU / 16; ++cb) {
+    if (cb * 16 >= w) break;
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < kT; ++t)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], sU[(4 * t + kq) * kWinU + cb * 16 + lr], acc, 0, 0, 0);
+    const int col = cb * 16 + lr;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rb * 16 + kq + 4 * v;
+      if (row < m && col < w) X0[(int64_t)row * sr + (int64_t)col * sj] = acc[v];
+    }
+  }
+}
+
+// One multi-bulge pass over rows/columns lo..hh of H (global, row-major, n x n) with Z (global,
+// Z(r, c) at ZT[c n + r]): wave b chases bulge b (shift pair sh[4 b .. 4 b + 3]) kMultiGap rows
+// behind bulge b - 1, as in the LDS-resident pass, but window by window (see above). sbuf: LDS
+// for the window and U. Called by every thread of the workgroup.
+__device__ void windowed_multibulge(double* __restrict__ H, int n, double* __restrict__ ZT, int lo, int hh, int nb,
+                                    const double* sh, double* sbuf) {
+  const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
+  double* sW = sbuf;
+  double* sU = sbuf + kWin * kWinLd;
+  const int nsteps = (hh - lo) + kMultiGap * (nb - 1);
+  int t = 0, a = lo;
+  while (t < nsteps) {
+    const int bw = min(a + kWin, hh + 1);  // window rows/columns a..bw-1
+    const int w = bw - a;
+    const bool last = bw == hh + 1;
+#define WW(r, c) sW[((r) - a) * kWinLd + ((c) - a)]
+    for (int i = tid; i < w * w; i += NT) {
+      const int r = i / w, c = i - (i / w) * w;
+      sW[r * kWinLd + c] = H[(int64_t)(a + r) * n + a + c];
+    }
+    for (int i = tid; i < kWin * kWinU; i += NT) {
+      const int r = i / kWinU, c = i - (i / kWinU) * kWinU;
+      sU[i] = (r == c && r < w) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // steps while the leading bulge's rows k..k+3 stay inside the window (all of them in the last)
+    const int t_end = last ? nsteps : min(nsteps, bw - 3 - lo);
+    for (; t < t_end; ++t) {
+      const int k = lo + t - kMultiGap * wv;
+      const bool on = wv < nb && k >= lo && k <= hh - 1;
+      const bool three = k < hh - 1;
+      double tau = 0.0, u1 = 0.0, u2 = 0.0, beta = 0.0;
+      if (on) {
+        double x, y, z;
+        if (k == lo) {  // the bulge enters: first column of (H - s1)(H - s2), product form (a == lo)
+          const double s1r = sh[4 * wv], s1i = sh[4 * wv + 1], s2r = sh[4 * wv + 2], s2i = sh[4 * wv + 3];
+          const double a0 = WW(lo, lo), a1 = WW(lo + 1, lo);
+          const double sc = fabs(a0 - s2r) + fabs(s2i) + fabs(a1);
+          const double a1s = a1 / sc;
+          x = a1s * WW(lo, lo + 1) + (a0 - s1r) * ((a0 - s2r) / sc) - s1i * (s2i / sc);
+          y = a1s * (a0 + WW(lo + 1, lo + 1) - s1r - s2r);
+          z = a1s * WW(lo + 2, lo + 1);
+        } else {
+          x = WW(k, k - 1);
+          y = WW(k + 1, k - 1);
+          z = three ? WW(k + 2, k - 1) : 0.0;
+        }
+        wave_sync();  // every lane has read its input before the left phase overwrites it
+        householder3(x, y, z, tau, u1, u2, beta);
+        if (tau != 0.0) {
+          if (lane == 0 && k > lo) {
+            WW(k, k - 1) = beta;
+            WW(k + 1, k - 1) = 0.0;
+            if (three) WW(k + 2, k - 1) = 0.0;
+          }
+          if (three) {
+            for (int c = k + lane; c < bw; c += 64) {
+              const double h0 = WW(k, c), h1 = WW(k + 1, c), h2 = WW(k + 2, c);
+              const double wl = tau * (h0 + u1 * h1 + u2 * h2);
+              WW(k, c) = h0 - wl;
+              WW(k + 1, c) = h1 - wl * u1;
+              WW(k + 2, c) = h2 - wl * u2;
+            }
+          } else {
+            for (int c = k + lane; c < bw; c += 64) {
+              const double h0 = WW(k, c), h1 = WW(k + 1, c);
+              const double wl = tau * (h0 + u1 * h1);
+              WW(k, c) = h0 - wl;
+              WW(k + 1, c) = h1 - wl * u1;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (on && tau != 0.0) {
+        const int rmax = min(k + 3, hh);
+        const int j = k - a;  // window column of the reflector
+        if (three) {
+          for (int r = a + lane; r <= rmax; r += 64) {
+            const double h0 = WW(r, k), h1 = WW(r, k + 1), h2 = WW(r, k + 2);
+            const double wr = tau * (h0 + u1 * h1 + u2 * h2);
+            WW(r, k) = h0 - wr;
+            WW(r, k + 1) = h1 - wr * u1;
+            WW(r, k + 2) = h2 - wr * u2;
+          }
+          for (int r = lane; r < w; r += 64) {
+            double* ur = sU + r * kWinU + j;
+            const double v0 = ur[0], v1 = ur[1], v2 = ur[2];
+            const double wr = tau * (v0 + u1 * v1 + u2 * v2);
+            ur[0] = v0 - wr;
+            ur[1] = v1 - wr * u1;
+            ur[2] = v2 - wr * u2;
+          }
+        } else {
+          for (int r = a + lane; r <= rmax; r += 64) {
+            const double h0 = WW(r, k), h1 = WW(r, k + 1);
+            const double wr = tau * (h0 + u1 * h1);
+            WW(r, k) = h0 - wr;
+            WW(r, k + 1) = h1 - wr * u1;
+          }
+          for (int r = lane; r < w; r += 64) {
+            double* ur = sU + r * kWinU + j;
+            const double v0 = ur[0], v1 = ur[1];
+            const double wr = tau * (v0 + u1 * v1);
+            ur[0] = v0 - wr;
+            ur[1] = v1 - wr * u1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+#undef WW
+    for (int i = tid; i < w * w; i += NT) {
+      const int r = i / w, c = i - (i / w) * w;
+      H[(int64_t)(a + r) * n + a + c] = sW[r * kWinLd + c];
+    }
+    // the window's transformation on Z (n rows), on the rows above the window and, transposed,
+    // on the columns right of it: disjoint blocks, 16 rows per wave task
+    const int bz = (n + 15) >> 4, ba = (a + 15) >> 4, br = (n - bw + 15) >> 4;
+    for (int q = wv; q < bz + ba + br; q += nw) {
+      if (q < bz)
+        window_update_rows(ZT + (int64_t)a * n, 1, n, n, w, sU, q, lane);
+      else if (q < bz + ba)
+        window_update_rows(H + a, n, 1, a, w, sU, q - bz, lane);
+      else
+        window_update_rows(H + (int64_t)a * n + bw, 1, n, n - bw, w, sU, q - bz - ba, lane);
+    }
+    __syncthreads();
+    // next window: one row above the trailing bulge's next reflector row
+    a = max(lo, lo + t - kMultiGap * (nb - 1) - 1);
+  }
+}
+
 template <bool kLds>
 __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t* status, double* sH, double* srefl,
                                            double* sred, int* sctl, double* sxyz, ZOp* zops, int sweep_cap) {
@@ -809,7 +1038,9 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     }
     __syncthreads();
     const ZOp op = zops[slot];  // not rewritten before the barrier of the next iteration
-    if (op.nb > 0) {
+    if (!kLds && op.nb > 0 && n <= kWinMaxN) {
+      windowed_multibulge(H, n, ZT, op.lo, op.hh, op.nb, srefl + slot * 3 * kMaxn, sH);
+    } else if (op.nb > 0) {
       // Multi-bulge pass: wave b chases bulge b, kMultiGap rows behind bulge b - 1. A chain step
       // moves every bulge one row: each wave forms its reflector (from column k - 1, or from the
       // shift polynomial when it enters at row lo), applies it from the left to rows k..k+2,
@@ -1231,22 +1462,35 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
 #undef ZZ
 }
 
-// One workgroup per problem: workgroup b solves items[order[b]] (order null: items[b]).
+// One workgroup per problem of at most kLdsMaxn rows: workgroup b solves items[order[b]] (order
+// null: items[b]); larger problems are left to k_eigen_big.
 __global__ __launch_bounds__(kEigenThreads) void k_eigen(const Item* items, double* ws, int32_t* status,
                                                           int sweep_cap, const int32_t* order) {
   const Item it = items[order ? order[blockIdx.x] : blockIdx.x];
-  if (status[it.layer] != 0) return;
+  if (status[it.layer] != 0 || it.n > kLdsMaxn) return;
   __shared__ double sH[kLdsMaxn * (kLdsMaxn + 1) + 3 * 64];
   __shared__ double srefl[2 * 3 * kMaxn];
   __shared__ double sred[16];
   __shared__ int sctl[8];
   __shared__ double sxyz[3];
   __shared__ ZOp zops[2];
-  double* base = ws + it.ws;
-  if (it.n <= kLdsMaxn)
-    eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
-  else
-    eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+  eigen_body<true>(it, ws + it.ws, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+}
+
+// Problems larger than kLdsMaxn (H and Z in global memory, multi-bulge passes through an LDS
+// window): workgroup b solves items[order[b]] (order null: items[b]). A kernel of its own so that
+// its register allocation does not weigh on the LDS-resident path.
+__global__ __launch_bounds__(kEigenThreads) void k_eigen_big(const Item* items, double* ws, int32_t* status,
+                                                              int sweep_cap, const int32_t* order) {
+  const Item it = items[order ? order[blockIdx.x] : blockIdx.x];
+  if (status[it.layer] != 0 || it.n <= kLdsMaxn) return;
+  __shared__ double sbuf[kWin * kWinLd + kWin * kWinU];
+  __shared__ double srefl[2 * 3 * kMaxn];
+  __shared__ double sred[16];
+  __shared__ int sctl[8];
+  __shared__ double sxyz[3];
+  __shared__ ZOp zops[2];
+  eigen_body<false>(it, ws + it.ws, status, sbuf, srefl, sred, sctl, sxyz, zops, sweep_cap);
 }
 
 // Persistent form: every workgroup takes the next position of `order` from the counter `queue`
@@ -1269,12 +1513,8 @@ __global__ __launch_bounds__(kEigenThreads) void k_eigen_persistent(const Item* 
     const int pos = snext;
     if (pos >= n_items) return;
     const Item it = items[order[pos]];
-    if (status[it.layer] != 0) continue;
-    double* base = ws + it.ws;
-    if (it.n <= kLdsMaxn)
-      eigen_body<true>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
-    else
-      eigen_body<false>(it, base, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
+    if (status[it.layer] != 0 || it.n > kLdsMaxn) continue;
+    eigen_body<true>(it, ws + it.ws, status, sH, srefl, sred, sctl, sxyz, zops, sweep_cap);
   }
 }
 

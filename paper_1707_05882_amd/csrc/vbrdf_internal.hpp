@@ -100,7 +100,11 @@ __global__ void k_gemm(const Item* items, double* ws, int bufA, int bufB, int bu
 // persistent form takes positions of `order` from the counter `queue` (reset to 0 before the
 // launch) until n_items are taken.
 constexpr int kEigenPlanOrder = 0, kEigenLongestFirst = 1, kEigenPersistent = 2;
+// k_eigen and k_eigen_persistent solve the problems of at most kLdsMaxn rows (H in LDS);
+// k_eigen_big the larger ones, over the first n_big positions of the longest-first order (which
+// are exactly those), whatever the schedule.
 __global__ void k_eigen(const Item* items, double* ws, int32_t* status, int sweep_cap, const int32_t* order);
+__global__ void k_eigen_big(const Item* items, double* ws, int32_t* status, int sweep_cap, const int32_t* order);
 __global__ void k_eigen_persistent(const Item* items, double* ws, int32_t* status, int sweep_cap,
                                    const int32_t* order, int32_t* queue, int n_items);
 __global__ void k_reset_counter(int32_t* counter);
@@ -232,6 +236,7 @@ struct LaunchSet {
   const int32_t* order_d = nullptr;  // items by decreasing size (longest first)
   int32_t* queue_d = nullptr;        // work counter of the persistent eigensolver
   int persist_groups = 256;          // workgroups of the persistent eigensolver (compute units)
+  int n_big = 0;                     // items with n > kLdsMaxn (the first n_big positions of order_d)
   int qr_sweep_cap = 0;       // 0 = the eigensolver's default
   bool transmission = false;  // also write the per-order transmission T^m
   int precision = 0;          // VBRDF_PRECISION_*
