@@ -128,6 +128,12 @@ typedef struct vbrdf_plan_desc {
    * or a non-black base accept neither VBRDF_FLAG_SAVE_FOR_BACKWARD nor
    * VBRDF_FLAG_EMIT_TRANSMISSION. */
   int32_t base;
+  /* Off-node incidence (Sec. 2.C particular solution, eq. 28-33, in its half-size form of Sec. 3.B,
+   * eq. 46-48): n_mu0 incident cosines (host array mu0[n_mu0], each in (0, 1], at most 64 and at
+   * most N of every layer), for which vbrdf_solve_ex also writes the BRDF towards the Gauss nodes.
+   * 0 = none. Not with stacks, a reflecting base or VBRDF_FLAG_SAVE_FOR_BACKWARD. */
+  int32_t n_mu0;
+  const double* mu0;
 } vbrdf_plan_desc;
 
 /* ABI version of the loaded library (VBRDF_ABI_VERSION). */
@@ -199,6 +205,27 @@ vbrdf_status vbrdf_solve_base(vbrdf_plan* plan, const double* tau, const double*
 
 /* Bytes of base data vbrdf_solve_base reads for this plan (0 for a black base). */
 size_t vbrdf_plan_base_bytes(const vbrdf_plan* plan);
+
+/* The general solve: vbrdf_solve_base plus, for a plan with off-node beams (n_mu0 > 0), the BRDF
+ * of each beam towards the Gauss nodes:
+ *   F_beam    device doubles, per layer [N_out = i][n_mu0 = j][n_dphi = k][4 = r][4 = p], packed
+ *             back to back (vbrdf_plan_beam_bytes() bytes): F_r for incidence at mu0_j, outgoing
+ *             node i, azimuth difference 2 pi k / n_dphi, referred to the horizontal irradiance
+ *             mu0_j I0 as the node table.
+ * Per order the particular solution of the beam's source is found through the eigen-decomposition
+ * of the half-size problem, (F E - mu0^-2) G = (F X+ + X- / mu0) M^-1 (eq. 47) solved as
+ * U (Lambda - mu0^-2)^-1 U^-1, and the homogeneous part that cancels its incoming diffuse light at
+ * the top and the black base comes from the layer's boundary operators. A beam within a relative
+ * 1e-12 of a resonance (mu0^-2 equal to an eigenvalue of FE, which in weakly scattering orders
+ * happens at the Gauss nodes, where the node table is exact) makes the layer NUMERIC.
+ * base and the other arguments as for vbrdf_solve_base (base NULL for a black base). vbrdf_solve
+ * on a plan with beams computes the node table only. Errors: INVALID (null pointers; F_beam NULL
+ * for a plan with beams), as vbrdf_solve. */
+vbrdf_status vbrdf_solve_ex(vbrdf_plan* plan, const double* tau, const double* omega, const double* coef,
+                            const double* base, double* F_r, double* F_beam, int32_t* layer_status, void* stream);
+
+/* Bytes of F_beam a plan writes (0 without beams). */
+size_t vbrdf_plan_beam_bytes(const vbrdf_plan* plan);
 
 /* Inspection of the last solve's per-order intermediates for one (layer, order), copied
  * synchronously (after waiting for `stream`) into caller-owned host arrays:

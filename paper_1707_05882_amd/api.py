@@ -35,6 +35,15 @@ class BRDFSolver:
         for n, p, s in zip(self.plan.N, self.plan.n_dphi, sizes):
             self._views.append(self.F[off:off + s].view(n, n, p, 4, 4))
             off += s
+        self.F_beam = None
+        self._beam_views = []
+        if self.plan.mu0:
+            nb = len(self.plan.mu0)
+            self.F_beam = torch.empty(self.plan.beam_bytes() // 8, dtype=torch.float64, device=self.device)
+            off = 0
+            for n, p in zip(self.plan.N, self.plan.n_dphi):
+                self._beam_views.append(self.F_beam[off:off + n * nb * p * 16].view(n, nb, p, 4, 4))
+                off += n * nb * p * 16
 
     def upload(self, tau, omega, coefs):
         dev = self.device
@@ -47,7 +56,9 @@ class BRDFSolver:
         """Enqueue on `stream` (default: torch's current stream) with device-resident inputs
         (base_d: the base data of a plan with a reflecting base)."""
         s = torch.cuda.current_stream(self.device) if stream is None else stream
-        if self.plan.below is None and self.plan.base == binding.BASE_BLACK:
+        if self.F_beam is not None:
+            self.plan.solve_ex(tau_d, omega_d, coef_d, base_d, self.F, self.F_beam, self.status, s.cuda_stream)
+        elif self.plan.below is None and self.plan.base == binding.BASE_BLACK:
             self.plan.solve(tau_d, omega_d, coef_d, self.F, self.status, s.cuda_stream)
         else:
             self.plan.solve_base(tau_d, omega_d, coef_d, base_d, self.F, self.status, s.cuda_stream)
@@ -69,6 +80,10 @@ class BRDFSolver:
 
     def layer(self, i):
         return self._views[i]
+
+    def beams(self, i):
+        """(N, n_mu0, n_dphi, 4, 4) view of layer i's off-node beam BRDF (plans built with mu0)."""
+        return self._beam_views[i]
 
 
 class VbrdfFunction(torch.autograd.Function):
@@ -154,6 +169,16 @@ class SpectralBRDF:
 
 _PRECISIONS = {"fp64": binding.PRECISION_FP64, "fp32_refined": binding.PRECISION_FP32_REFINED}
 _BASES = {"black": binding.BASE_BLACK, "lambertian": binding.BASE_LAMBERTIAN, "mueller": binding.BASE_MUELLER}
+
+
+def brdf_beam(tau, omega, coef, N, M, n_dphi, mu0, precision="fp64", device="cuda"):
+    """BRDF of one layer for incidence at arbitrary cosines mu0 (a sequence, each in (0, 1]) towards
+    the Gauss nodes: a (N, len(mu0), n_dphi, 4, 4) float64 tensor (outgoing node i, incident j,
+    azimuth difference 2 pi k / n_dphi, Mueller row, column)."""
+    L = np.asarray(coef).shape[1]
+    s = BRDFSolver([N], [L], [M], [n_dphi], device=device, precision=_PRECISIONS[precision], mu0=mu0)
+    s([tau], [omega], [coef])
+    return s.beams(0).clone()
 
 
 def stack_brdf(tau, omega, coef, N, M, n_dphi, base="black", rho=0.0, Rb=None, precision="fp64", device="cuda"):

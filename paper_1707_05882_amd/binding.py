@@ -43,8 +43,10 @@ EXPORTED = (
     "vbrdf_workspace_query", "vbrdf_plan_destroy", "vbrdf_plan_output_bytes", "vbrdf_plan_workspace_bytes",
     "vbrdf_solve", "vbrdf_plan_inspect", "vbrdf_radiance", "vbrdf_plan_stage_times", "vbrdf_stage_name",
     "vbrdf_solve_noalloc", "vbrdf_backward", "vbrdf_plan_get_tuning", "vbrdf_plan_set_tuning",
-    "vbrdf_plan_autotune", "vbrdf_solve_base", "vbrdf_plan_base_bytes",
+    "vbrdf_plan_autotune", "vbrdf_solve_base", "vbrdf_plan_base_bytes", "vbrdf_solve_ex",
+    "vbrdf_plan_beam_bytes",
 )
+MAX_BEAMS = 64
 EIGEN_PLAN_ORDER = 0
 EIGEN_LONGEST_FIRST = 1
 EIGEN_PERSISTENT = 2
@@ -77,6 +79,8 @@ class PlanDesc(ctypes.Structure):
         ("refine_steps", ctypes.c_int32),
         ("below", ctypes.POINTER(ctypes.c_int32)),
         ("base", ctypes.c_int32),
+        ("n_mu0", ctypes.c_int32),
+        ("mu0", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -132,6 +136,10 @@ def load():
     L.vbrdf_solve_base.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.vbrdf_plan_base_bytes.restype = ctypes.c_size_t
     L.vbrdf_plan_base_bytes.argtypes = [vp]
+    L.vbrdf_solve_ex.restype = i32
+    L.vbrdf_solve_ex.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.vbrdf_plan_beam_bytes.restype = ctypes.c_size_t
+    L.vbrdf_plan_beam_bytes.argtypes = [vp]
     if L.vbrdf_abi_version() != ABI_VERSION:
         raise OSError("libvbrdf.so ABI version mismatch")
     _lib = L
@@ -184,7 +192,7 @@ class _Desc:
     """Keeps a PlanDesc and the shape arrays it points to alive together."""
 
     def __init__(self, N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes,
-                 qr_sweep_cap, refine_steps=0, below=None, base=BASE_BLACK):
+                 qr_sweep_cap, refine_steps=0, below=None, base=BASE_BLACK, mu0=None):
         self.N, self.L, self.M, self.n_dphi = (_as_list(v) for v in (N, L, M, n_dphi))
         nl = len(self.N)
         if not (len(self.L) == len(self.M) == len(self.n_dphi) == nl):
@@ -199,14 +207,22 @@ class _Desc:
                 raise ValueError("below needs one entry per layer")
             bl = arr(below)
             self.keep.append(bl)
+        m0 = None
+        n_mu0 = 0
+        if mu0 is not None:
+            vals = [float(x) for x in np.atleast_1d(mu0)]
+            n_mu0 = len(vals)
+            m0 = (ctypes.c_double * max(n_mu0, 1))(*vals)
+            self.keep.append(m0)
         self.desc = PlanDesc(ABI_VERSION, nl, *self.keep[:4], int(precision), int(flags), int(workspace_cap_bytes),
-                             ws, int(workspace_bytes), int(qr_sweep_cap), int(refine_steps), bl, int(base))
+                             ws, int(workspace_bytes), int(qr_sweep_cap), int(refine_steps), bl, int(base),
+                             n_mu0, ctypes.cast(m0, ctypes.POINTER(ctypes.c_double)) if m0 is not None else None)
         self.n_layers = nl
 
 
-def workspace_query(N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, below=None, base=BASE_BLACK):
+def workspace_query(N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, below=None, base=BASE_BLACK, mu0=None):
     """Bytes of device workspace a plan of these shapes needs (host call)."""
-    d = _Desc(N, L, M, n_dphi, precision, flags, 0, None, 0, 0, 0, below, base)
+    d = _Desc(N, L, M, n_dphi, precision, flags, 0, None, 0, 0, 0, below, base, mu0)
     out = ctypes.c_uint64()
     _check(load().vbrdf_workspace_query(ctypes.byref(d.desc), ctypes.byref(out)))
     return int(out.value)
@@ -216,9 +232,11 @@ class Plan:
     """Owns a vbrdf_plan. Shapes are per-layer lists (or scalars for one layer)."""
 
     def __init__(self, N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, workspace_cap_bytes=0,
-                 workspace=None, workspace_bytes=0, qr_sweep_cap=0, refine_steps=0, below=None, base=BASE_BLACK):
+                 workspace=None, workspace_bytes=0, qr_sweep_cap=0, refine_steps=0, below=None, base=BASE_BLACK,
+                 mu0=None):
         d = _Desc(N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes, qr_sweep_cap,
-                  refine_steps, below, base)
+                  refine_steps, below, base, mu0)
+        self.mu0 = None if mu0 is None else [float(x) for x in np.atleast_1d(mu0)]
         self.below = None if below is None else [int(b) for b in below]
         self.base = int(base)
         self.N, self.L, self.M, self.n_dphi = d.N, d.L, d.M, d.n_dphi
@@ -254,6 +272,14 @@ class Plan:
 
     def base_bytes(self):
         return load().vbrdf_plan_base_bytes(self._h)
+
+    def solve_ex(self, tau, omega, coef, base, F_r, F_beam, layer_status, stream=0):
+        """vbrdf_solve_ex: stacks, bases and off-node beams (device pointers; None where absent)."""
+        _check(load().vbrdf_solve_ex(self._h, _ptr(tau), _ptr(omega), _ptr(coef), _ptr(base), _ptr(F_r),
+                                     _ptr(F_beam), _ptr(layer_status), ctypes.c_void_p(int(stream))))
+
+    def beam_bytes(self):
+        return load().vbrdf_plan_beam_bytes(self._h)
 
     def get_tuning(self):
         t = Tuning()

@@ -122,8 +122,9 @@ struct vbrdf_plan : LaunchSet {
   bool timing = false;
   bool graph = false;             // capture the solve into a hipGraph and replay it
   hipGraphExec_t gexec = nullptr;  // instantiated for the pointers in gkey
-  const void* gkey[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void* gkey[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   size_t base_doubles = 0;  // base data a solve reads (vbrdf_plan_base_bytes / 8)
+  size_t beam_doubles = 0;  // off-node beam output (vbrdf_plan_beam_bytes / 8)
   int timed = 0;  // solves recorded since the last stage_times query (capped at kTimedSolves)
   std::vector<hipEvent_t> ev;  // kTimedSolves sets of kNumStages + 1 events
 
@@ -143,6 +144,8 @@ struct vbrdf_plan : LaunchSet {
     if (base_off_d) (void)hipFree(const_cast<int64_t*>(base_off_d));
     if (stack_items_d) (void)hipFree(const_cast<Item*>(stack_items_d));
     if (stack_tasks_d) (void)hipFree(const_cast<StackTask*>(stack_tasks_d));
+    if (mu0_d) (void)hipFree(const_cast<double*>(mu0_d));
+    if (btasks_d) (void)hipFree(const_cast<BeamTask*>(btasks_d));
   }
 };
 
@@ -232,6 +235,17 @@ static vbrdf_status check_desc(const vbrdf_plan_desc* d) {
   if ((stacks || d->base != VBRDF_BASE_BLACK) &&
       (d->flags & (VBRDF_FLAG_SAVE_FOR_BACKWARD | VBRDF_FLAG_EMIT_TRANSMISSION)))
     return fail(VBRDF_E_UNSUPPORTED, "stacks and reflecting bases take neither SAVE_FOR_BACKWARD nor EMIT_TRANSMISSION");
+  if (d->n_mu0 < 0 || d->n_mu0 > kMaxBeams)
+    return fail(VBRDF_E_INVALID, "n_mu0 must lie in [0, %d] (got %d)", kMaxBeams, d->n_mu0);
+  if (d->n_mu0 > 0) {
+    if (!d->mu0) return fail(VBRDF_E_INVALID, "null mu0 array");
+    for (int j = 0; j < d->n_mu0; ++j)
+      if (!(d->mu0[j] > 0.0 && d->mu0[j] <= 1.0)) return fail(VBRDF_E_INVALID, "mu0[%d] outside (0, 1]", j);
+    for (int l = 0; l < d->n_layers; ++l)
+      if (d->n_mu0 > d->N[l]) return fail(VBRDF_E_INVALID, "n_mu0 = %d exceeds N = %d of layer %d", d->n_mu0, d->N[l], l);
+    if (stacks || d->base != VBRDF_BASE_BLACK || (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD))
+      return fail(VBRDF_E_UNSUPPORTED, "off-node beams take neither stacks, a reflecting base nor SAVE_FOR_BACKWARD");
+  }
   return VBRDF_OK;
 }
 
@@ -310,7 +324,9 @@ static vbrdf_status build_stacks(vbrdf_plan* p, const vbrdf_plan_desc* d) {
 }
 
 // Per-item workspace blocks, 256-byte aligned.
-static int64_t block_doubles(int N, int L, bool save) { return block_doubles_of(4 * N, N, L, save); }
+static int64_t block_doubles(int N, int L, bool save, int n_mu0) {
+  return n_mu0 > 0 ? block_doubles_beams(4 * N, N, L, n_mu0) : block_doubles_of(4 * N, N, L, save);
+}
 
 vbrdf_status vbrdf_workspace_query(const vbrdf_plan_desc* d, uint64_t* bytes) {
   if (!bytes) return fail(VBRDF_E_INVALID, "null output pointer");
@@ -319,7 +335,7 @@ vbrdf_status vbrdf_workspace_query(const vbrdf_plan_desc* d, uint64_t* bytes) {
   if (st != VBRDF_OK) return st;
   int64_t total = 0;
   const bool save = (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0;
-  for (int l = 0; l < d->n_layers; ++l) total += (int64_t)d->M[l] * block_doubles(d->N[l], d->L[l], save);
+  for (int l = 0; l < d->n_layers; ++l) total += (int64_t)d->M[l] * block_doubles(d->N[l], d->L[l], save, d->n_mu0);
   *bytes = (uint64_t)total * sizeof(double);
   return VBRDF_OK;
 }
@@ -335,7 +351,8 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
   p->n_layers = d->n_layers;
   std::vector<double> quad;
   std::vector<SynthTask> tasks;
-  int64_t coef_off = 0, out_off = 0, ws_off = 0;
+  int64_t coef_off = 0, out_off = 0, ws_off = 0, beam_off = 0;
+  std::vector<BeamTask> btasks;
   for (int l = 0; l < d->n_layers; ++l) {
     Layer ly{};
     ly.N = d->N[l];
@@ -346,6 +363,10 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     ly.out_off = out_off;
     ly.quad_off = (int64_t)quad.size();
     ly.item0 = (int64_t)p->items_h.size();
+    ly.beam_off = beam_off;
+    beam_off += (int64_t)ly.N * d->n_mu0 * ly.n_dphi * 16;
+    for (int i = 0; i < ly.N; ++i)
+      for (int j = 0; j < d->n_mu0; ++j) btasks.push_back(BeamTask{l, i, j, 0});
     std::vector<double> x, w;
     gauss_legendre(ly.N, x, w);
     for (int i = 0; i < ly.N; ++i) quad.push_back(0.5 * (1.0 + x[i]));
@@ -359,7 +380,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       it.L = ly.L;
       it.n = n;
       it.ws = ws_off;
-      ws_off += block_doubles(ly.N, ly.L, (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0);
+      ws_off += block_doubles(ly.N, ly.L, (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0, d->n_mu0);
       p->items_h.push_back(it);
     }
     for (int i = 0; i < ly.N; ++i)
@@ -480,6 +501,22 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     }
   }
   p->base_kind = d->base;
+  if (d->n_mu0 > 0) {
+    std::vector<double> mu0(d->mu0, d->mu0 + d->n_mu0);
+    double* mu0_d = nullptr;
+    BeamTask* bt_d = nullptr;
+    vbrdf_status bs = upload(mu0, &mu0_d);
+    p->mu0_d = mu0_d;
+    if (bs == VBRDF_OK) bs = upload(btasks, &bt_d);
+    p->btasks_d = bt_d;
+    if (bs != VBRDF_OK) {
+      delete p;
+      return bs;
+    }
+    p->n_mu0 = d->n_mu0;
+    p->n_btasks = (int)btasks.size();
+    p->beam_doubles = (size_t)beam_off;
+  }
   if (d->below || d->base != VBRDF_BASE_BLACK) {
     const vbrdf_status sst = build_stacks(p, d);
     if (sst != VBRDF_OK) {
@@ -509,7 +546,9 @@ static void enqueue_stacks(const LaunchSet& ls, const double* base, int32_t* lay
 // The launch sequence of one solve on stream s; when evs is given, kNumSolveStages + 1 events are
 // recorded around and between the stages.
 void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef,
-                   const double* base, double* F_r, int32_t* layer_status, hipStream_t s, hipEvent_t* evs) {
+                   const double* base, double* F_r, double* F_beam, int32_t* layer_status, hipStream_t s,
+                   hipEvent_t* evs) {
+  const bool beams = ls.n_mu0 > 0 && F_beam;
   const LaunchSet* p = &ls;
   const int ni = p->n_items, mn = p->max_n, mN = p->max_N;
   int stage = 0;
@@ -571,6 +610,7 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   k_refine_delta<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->ws_d, layer_status);
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, kBufZ, 0, layer_status);  // U (I + X) Q
   k_refine_commit<<<dim3((mn * mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
+  if (beams) enqueue_beam_particular(*p, omega, coef, layer_status, s);  // needs F~, before the boundary solve
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, kBufU, kBufG, 0, layer_status);  // V = E~ U
   mark();
@@ -611,6 +651,7 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
     launch_trsm(p->trsm_rows, xg, p->trsm_lds, s, p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, trb);
     mark();
   }
+  if (beams) enqueue_beam_response(*p, tau, layer_status, s);
   const int rmode = p->stacked ? kResponseBrackets : (p->transmission ? kResponseTransmission : 0);
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status,
                                                        rmode);
@@ -618,6 +659,7 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   if (p->stacked) enqueue_stacks(*p, base, layer_status, s);
   mark();
   k_synth<<<p->n_tasks, 256, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
+  if (beams) enqueue_beam_synth(*p, F_beam, layer_status, s);
   if (p->save) k_copy_status<<<(p->n_layers + 255) / 256, 256, 0, s>>>(layer_status, p->status_d, p->n_layers);
   mark();
 }
@@ -700,20 +742,21 @@ void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omeg
 extern "C" {
 
 static vbrdf_status solve_impl(vbrdf_plan* p, const double* tau, const double* omega, const double* coef,
-                               const double* base, double* F_r, int32_t* layer_status, void* stream) {
+                               const double* base, double* F_r, double* F_beam, int32_t* layer_status,
+                               void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (p->graph) {
     if (!s) return fail(VBRDF_E_INVALID, "graph replay needs a non-default stream");
-    const void* key[7] = {tau, omega, coef, F_r, layer_status, stream, base};
+    const void* key[8] = {tau, omega, coef, F_r, layer_status, stream, base, F_beam};
     bool same = p->gexec != nullptr;
-    for (int i = 0; i < 7; ++i) same = same && key[i] == p->gkey[i];
+    for (int i = 0; i < 8; ++i) same = same && key[i] == p->gkey[i];
     if (!same) {
       if (p->gexec) {
         HIP_TRY(hipGraphExecDestroy(p->gexec));
         p->gexec = nullptr;
       }
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      enqueue_solve(*p, tau, omega, coef, base, F_r, layer_status, s, nullptr);
+      enqueue_solve(*p, tau, omega, coef, base, F_r, F_beam, layer_status, s, nullptr);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(s, &g);
       if (ec != hipSuccess) return fail(VBRDF_E_DEVICE, "stream capture: %s", hipGetErrorString(ec));
@@ -723,7 +766,7 @@ static vbrdf_status solve_impl(vbrdf_plan* p, const double* tau, const double* o
         p->gexec = nullptr;
         return fail(VBRDF_E_DEVICE, "graph instantiation: %s", hipGetErrorString(ei));
       }
-      for (int i = 0; i < 7; ++i) p->gkey[i] = key[i];
+      for (int i = 0; i < 8; ++i) p->gkey[i] = key[i];
     }
     HIP_TRY(hipGraphLaunch(p->gexec, s));
     p->solved = true;
@@ -731,7 +774,7 @@ static vbrdf_status solve_impl(vbrdf_plan* p, const double* tau, const double* o
   }
   const bool rec = p->timing && p->timed < kTimedSolves;
   p->solved = true;
-  enqueue_solve(*p, tau, omega, coef, base, F_r, layer_status, s,
+  enqueue_solve(*p, tau, omega, coef, base, F_r, F_beam, layer_status, s,
                 rec ? &p->ev[(size_t)p->timed * (kNumStages + 1)] : nullptr);
   if (rec) ++p->timed;
   HIP_TRY(hipGetLastError());
@@ -744,7 +787,7 @@ vbrdf_status vbrdf_solve(vbrdf_plan* p, const double* tau, const double* omega, 
   if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
   if (p->base_kind != VBRDF_BASE_BLACK)
     return fail(VBRDF_E_INVALID, "the plan has a reflecting base: its data go through vbrdf_solve_base");
-  return solve_impl(p, tau, omega, coef, nullptr, F_r, layer_status, stream);
+  return solve_impl(p, tau, omega, coef, nullptr, F_r, nullptr, layer_status, stream);
 }
 
 vbrdf_status vbrdf_solve_base(vbrdf_plan* p, const double* tau, const double* omega, const double* coef,
@@ -752,9 +795,21 @@ vbrdf_status vbrdf_solve_base(vbrdf_plan* p, const double* tau, const double* om
   if (!p) return fail(VBRDF_E_INVALID, "null plan");
   if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
   if (p->base_kind != VBRDF_BASE_BLACK && !base) return fail(VBRDF_E_INVALID, "null base data for a reflecting base");
-  return solve_impl(p, tau, omega, coef, p->base_kind == VBRDF_BASE_BLACK ? nullptr : base, F_r, layer_status,
-                    stream);
+  return solve_impl(p, tau, omega, coef, p->base_kind == VBRDF_BASE_BLACK ? nullptr : base, F_r, nullptr,
+                    layer_status, stream);
 }
+
+vbrdf_status vbrdf_solve_ex(vbrdf_plan* p, const double* tau, const double* omega, const double* coef,
+                            const double* base, double* F_r, double* F_beam, int32_t* layer_status, void* stream) {
+  if (!p) return fail(VBRDF_E_INVALID, "null plan");
+  if (!tau || !omega || !coef || !F_r || !layer_status) return fail(VBRDF_E_INVALID, "null device pointer");
+  if (p->base_kind != VBRDF_BASE_BLACK && !base) return fail(VBRDF_E_INVALID, "null base data for a reflecting base");
+  if (p->n_mu0 > 0 && !F_beam) return fail(VBRDF_E_INVALID, "null beam output for a plan with off-node beams");
+  return solve_impl(p, tau, omega, coef, p->base_kind == VBRDF_BASE_BLACK ? nullptr : base, F_r,
+                    p->n_mu0 > 0 ? F_beam : nullptr, layer_status, stream);
+}
+
+size_t vbrdf_plan_beam_bytes(const vbrdf_plan* p) { return p ? p->beam_doubles * sizeof(double) : 0; }
 
 size_t vbrdf_plan_base_bytes(const vbrdf_plan* p) { return p ? p->base_doubles * sizeof(double) : 0; }
 
@@ -840,7 +895,7 @@ vbrdf_status vbrdf_plan_autotune(vbrdf_plan* p, const double* tau, const double*
     for (int c = 0; c < 3; ++c) {
       p->eigen_mode = cand_e[c];
       set_trsm_rows(p, cand_r[c]);
-      enqueue_solve(*p, tau, omega, coef, nullptr, F_r, layer_status, s, ev.data());
+      enqueue_solve(*p, tau, omega, coef, nullptr, F_r, nullptr, layer_status, s, ev.data());
       hipError_t e = hipEventSynchronize(ev[kNumSolveStages]);
       float te = 0.0f, tr = 0.0f;
       if (e == hipSuccess) e = hipEventElapsedTime(&te, ev[eig_stage], ev[eig_stage + 1]);
@@ -863,7 +918,7 @@ vbrdf_status vbrdf_plan_autotune(vbrdf_plan* p, const double* tau, const double*
   p->eigen_mode = pick_e;
   set_trsm_rows(p, pick_r);
   if (st == VBRDF_OK) {  // leave the result of the chosen configuration behind
-    enqueue_solve(*p, tau, omega, coef, nullptr, F_r, layer_status, s, nullptr);
+    enqueue_solve(*p, tau, omega, coef, nullptr, F_r, nullptr, layer_status, s, nullptr);
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = fail(VBRDF_E_DEVICE, "autotune: %s", hipGetErrorString(e));
   }

@@ -229,3 +229,152 @@ __global__ __launch_bounds__(256) void k_assemble(const Item* items, const Layer
 }
 
 }  // namespace vbrdf
+
+namespace vbrdf {
+
+// ---- off-node incidence: Legendre table and source at the incident cosines mu0_j
+
+// leg0[(l * n_mu0 + j) * 3 + {0,1,2}] = (Pb, R, T) of order m at mu0_j, as k_legendre at the nodes.
+__global__ __launch_bounds__(kLegThreads) void k_beam_legendre(const Item* items, const double* mu0, int n_mu0,
+                                                               double* ws, const int32_t* status) {
+  const Item it = items[blockIdx.x];
+  if (status[it.layer] != 0) return;
+  const int L = it.L, m = it.m;
+  double* leg = ws + it.ws + beam_leg_off(it.n, it.N, it.L);
+  const int seq = threadIdx.x / 128, j = threadIdx.x % 128;
+  if (j < n_mu0) {
+    const double x = mu0[j];
+    const int nn = seq == 0 ? 0 : (seq == 1 ? 2 : -2);
+    WSeq q{m, nn, seq == 0 ? m : (m > 2 ? m : 2), 0.0, 0.0};
+    for (int l = 0; l < L; ++l) {
+      const double d = wseq_value(q, l, x);
+      leg[((int64_t)l * n_mu0 + j) * 3 + seq] = (l < m) ? 0.0 : d;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < L * n_mu0; t += blockDim.x) {
+    double* o = leg + (int64_t)t * 3;
+    const double dp = o[1], dm = o[2];
+    o[1] = -0.5 * (dp + dm);
+    o[2] = -0.5 * (dp - dm);
+  }
+}
+
+// The order-m source of a unit Stokes beam e_p at mu0_j (Sec. 2.C, eq. 28; the per-order phase
+// function normalisation of the rest of the solve): X(+-mu_i) = omega/(2 pi) A^m(+-mu_i, mu0_j) e_p.
+// In the half-size form only the mirrored sum and difference enter, X_s = X+ + D X- and
+// X_d = X+ - D X-, which are the blocks of S+ and S- with their second Legendre factor taken at
+// mu0_j. Written scaled for the particular solve: kBufB0 = M^-1 X_s, kBufB1 = M^-1 X_d / mu0_j
+// (column 4 j + p); the columns of the n x n buffers beyond the beams are zeroed. Grid as
+// k_assemble, the column tiles running over the N node columns.
+__global__ __launch_bounds__(256) void k_beam_source(const Item* items, const Layer* layers, const double* quad,
+                                                     const double* omega, const double* coef, const double* mu0,
+                                                     int n_mu0, double* ws, const int32_t* status) {
+  const Item it = items[blockIdx.z];
+  if (status[it.layer] != 0) return;
+  const int N = it.N, L = it.L, m = it.m, n = it.n;
+  const int i0 = blockIdx.y * kAsmTile, j0 = blockIdx.x * kAsmTile;
+  if (i0 >= N || j0 >= N) return;
+  const Layer ly = layers[it.layer];
+  const double* leg = ws + it.ws + leg_off(n);
+  const double* leg0 = ws + it.ws + beam_leg_off(n, N, L);
+  const double* cf = coef + ly.coef_off;
+  double* X0 = buf_ptr(ws, it, kBufB0);
+  double* X1 = buf_ptr(ws, it, kBufB1);
+  __shared__ double sPi[kAsmChunk][kAsmTile][3];
+  __shared__ double sPj[kAsmChunk][kAsmTile][3];
+  __shared__ double sC[6][kAsmChunk];
+  const int tid = threadIdx.x;
+  const int ti = tid / kAsmTile, tj = tid % kAsmTile;
+  const int i = i0 + ti, j = j0 + tj;
+  if (j0 >= n_mu0) {  // columns beyond the beams
+    if (i < N && j < N)
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+          const int64_t idx = (int64_t)(4 * i + r) * n + 4 * j + c;
+          X0[idx] = 0.0;
+          X1[idx] = 0.0;
+        }
+    return;
+  }
+  double q[2][9], u[2][9];
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { q[e][k] = 0.0; u[e][k] = 0.0; }
+  for (int lc = m; lc < L; lc += kAsmChunk) {
+    const int cnt = min(kAsmChunk, L - lc);
+    __syncthreads();
+    for (int t = tid; t < cnt * kAsmTile * 3; t += blockDim.x) {
+      int l = t / (kAsmTile * 3), r = t % (kAsmTile * 3);
+      int a = r / 3, c = r % 3;
+      sPi[l][a][c] = (i0 + a < N) ? leg[((int64_t)(lc + l) * N + i0 + a) * 3 + c] : 0.0;
+      sPj[l][a][c] = (j0 + a < n_mu0) ? leg0[((int64_t)(lc + l) * n_mu0 + j0 + a) * 3 + c] : 0.0;
+    }
+    for (int t = tid; t < 6 * cnt; t += blockDim.x) {
+      int row = t / cnt, l = t % cnt;
+      sC[row][l] = cf[(int64_t)row * L + lc + l];
+    }
+    __syncthreads();
+    auto acc = [&](double* Q, double* U, int l) __attribute__((always_inline)) {
+      const double pi_ = sPi[l][ti][0], ri = sPi[l][ti][1], tI = sPi[l][ti][2];
+      const double pj = sPj[l][tj][0], rj = sPj[l][tj][1], tJ = sPj[l][tj][2];
+      const double a1 = sC[0][l], a2 = sC[1][l], a3 = sC[2][l], a4 = sC[3][l];
+      const double b1 = sC[4][l], b2 = sC[5][l];
+      Q[0] += pi_ * a1 * pj;
+      Q[1] += pi_ * b1 * rj;
+      Q[2] += pi_ * b1 * tJ;
+      Q[3] += ri * b1 * pj;
+      Q[4] += ri * a2 * rj;
+      Q[5] += ri * a2 * tJ;
+      Q[6] += tI * b1 * pj;
+      Q[7] += tI * a2 * rj;
+      Q[8] += tI * a2 * tJ;
+      U[0] += tI * a3 * tJ;
+      U[1] += tI * a3 * rj;
+      U[2] += tI * b2 * pj;
+      U[3] += ri * a3 * tJ;
+      U[4] += ri * a3 * rj;
+      U[5] += ri * b2 * pj;
+      U[6] += pi_ * b2 * tJ;
+      U[7] += pi_ * b2 * rj;
+      U[8] += pi_ * a4 * pj;
+    };
+    int l = 0;
+    for (; l + 1 < cnt; l += 2) {
+      acc(q[0], u[0], l);
+      acc(q[1], u[1], l + 1);
+    }
+    if (l < cnt) acc(q[0], u[0], l);
+  }
+  if (i >= N || j >= N) return;
+  auto iq = [&](int e, int r, int c) -> double {
+    if (r == 3 || c == 3) return 0.0;
+    const double* Q = q[e];
+    const double v[3][3] = {{Q[0], Q[1], -Q[2]}, {Q[3], Q[4], -Q[5]}, {-Q[6], -Q[7], Q[8]}};
+    return v[r][c];
+  };
+  auto uv = [&](int e, int r, int c) -> double {
+    if (r == 0 || c == 0) return 0.0;
+    const double* U = u[e];
+    const double v[3][3] = {{U[0], -U[1], -U[2]}, {-U[3], U[4], U[5]}, {U[6], -U[7], U[8]}};
+    return v[r - 1][c - 1];
+  };
+  const bool beam = j < n_mu0;
+  const double w = fmin(omega[it.layer], kOmegaMax);
+  const double sc = w / (2.0 * 3.141592653589793) / quad[ly.quad_off + i];
+  const double inv0 = beam ? 1.0 / mu0[j] : 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double sp = 2.0 * (iq(0, r, c) + uv(1, r, c));
+      const double sm = 2.0 * (uv(0, r, c) + iq(1, r, c));
+      const int64_t idx = (int64_t)(4 * i + r) * n + 4 * j + c;
+      X0[idx] = beam ? sc * sp : 0.0;
+      X1[idx] = beam ? sc * sm * inv0 : 0.0;
+    }
+  }
+}
+
+}  // namespace vbrdf

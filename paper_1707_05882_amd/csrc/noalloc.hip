@@ -176,7 +176,7 @@ extern "C" vbrdf_status vbrdf_solve_noalloc(int32_t N, int32_t L, int32_t M, int
   ls.trsm_lds = trsm_lds;
   ls.eigen_mode = kEigenPlanOrder;  // one layer: every order has the same size
   ls.n_big = n > kLdsMaxn ? M : 0;   // and the same eigensolver kernel (no order table needed)
-  enqueue_solve(ls, tau, omega, coef, nullptr, F_r, layer_status, s, nullptr);
+  enqueue_solve(ls, tau, omega, coef, nullptr, F_r, nullptr, layer_status, s, nullptr);
   e = hipGetLastError();
   if (e != hipSuccess) return vbrdf_fail(VBRDF_E_DEVICE, "launch: %s", hipGetErrorString(e));
   return VBRDF_OK;

@@ -38,6 +38,7 @@ struct Layer {
   int64_t out_off;   // doubles, into the caller's packed F_r array
   int64_t quad_off;  // doubles, into the plan's quadrature table (mu[N] then alpha[N])
   int64_t item0;     // index of this layer's m = 0 item
+  int64_t beam_off;  // doubles, into the caller's packed off-node beam output (plans with beams)
 };
 
 struct Item {
@@ -70,6 +71,24 @@ __host__ __device__ inline int64_t bwd_off(int n, int N, int L) { return (item_d
 __host__ __device__ inline int64_t block_doubles_of(int n, int N, int L, bool save) {
   return bwd_off(n, N, L) + (save ? (int64_t)kNumBwdBuf * n * n : 0);
 }
+// Off-node incidence ("beams", a plan option exclusive with the adjoint state): five n x n
+// matrices in the second group's slots, then the Legendre table at the incident cosines
+// [L][n_mu0][3]. The beams of an order occupy the first 4 n_mu0 columns (column 4 j + p: unit
+// Stokes p incident at mu0_j).
+constexpr int kNumBeamBuf = 5;
+enum BeamBuf : int { kBufB0 = kNumBuf, kBufB1, kBufB2, kBufB3, kBufB4 };
+static_assert(kNumBeamBuf <= kNumBwdBuf, "beam buffers use the adjoint's slots");
+__host__ __device__ inline int64_t beam_leg_off(int n, int N, int L) {
+  return bwd_off(n, N, L) + (int64_t)kNumBeamBuf * n * n;
+}
+__host__ __device__ inline int64_t block_doubles_beams(int n, int N, int L, int n_mu0) {
+  return (beam_leg_off(n, N, L) + (int64_t)L * n_mu0 * 3 + 31) / 32 * 32;
+}
+constexpr int kMaxBeams = 64;  // incident directions per plan
+
+struct BeamTask {  // one workgroup of the beam synthesis: (layer, outgoing node i, incident mu0_j)
+  int32_t layer, i, j, pad;
+};
 
 struct SynthTask {
   int32_t layer, i, q, pad;
@@ -253,6 +272,11 @@ struct LaunchSet {
   const StackTask* stack_tasks_d = nullptr; // matching tasks
   int n_levels = 0;
   int lvl_off[kMaxStackLevels + 1] = {};    // level k: stack items [lvl_off[k], lvl_off[k + 1])
+  // off-node incidence
+  int n_mu0 = 0;                            // incident directions (0: none)
+  const double* mu0_d = nullptr;            // their cosines
+  const BeamTask* btasks_d = nullptr;       // beam synthesis tasks
+  int n_btasks = 0;
 };
 constexpr int kBoundaryRefineSteps = 2;  // FP32-refined boundary solve: correction steps
 
@@ -262,7 +286,15 @@ int32_t vbrdf_fail(int32_t code, const char* fmt, ...);
 // Stages of the launch sequence (events are recorded around and between them when requested).
 constexpr int kNumSolveStages = 17;
 void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, const double* coef,
-                   const double* base, double* F_r, int32_t* layer_status, hipStream_t s, hipEvent_t* evs);
+                   const double* base, double* F_r, double* F_beam, int32_t* layer_status, hipStream_t s,
+                   hipEvent_t* evs);
+// ---- off-node incidence (k_beam.hip): the half-size particular solution (eq. 46-48), before the
+// boundary factorisation overwrites F~; the response through the boundary operators after the right
+// divisions; the synthesis of the beam BRDF.
+void enqueue_beam_particular(const LaunchSet& ls, const double* omega, const double* coef, int32_t* status,
+                             hipStream_t s);
+void enqueue_beam_response(const LaunchSet& ls, const double* tau, int32_t* status, hipStream_t s);
+void enqueue_beam_synth(const LaunchSet& ls, double* F_beam, const int32_t* status, hipStream_t s);
 void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omega, const double* dF, double* dtau,
                       double* domega, double* dcoef, hipStream_t s);
 

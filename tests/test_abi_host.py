@@ -81,6 +81,15 @@ def test_gauss_nodes_rejects_bad_order():
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], base=1, flags=8), binding.E_UNSUPPORTED),  # base + adjoint
     (dict(N=[8] * 65, L=[4] * 65, M=[2] * 65, n_dphi=[8] * 65, below=list(range(1, 65)) + [-1]),
      binding.E_UNSUPPORTED),  # deeper than 64 layers
+    # off-node beams
+    (dict(N=[4], L=[4], M=[2], n_dphi=[8], mu0=[0.1, 0.2, 0.3, 0.4, 0.5]), binding.E_INVALID),  # n_mu0 > N
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], mu0=[0.5, 0.0]), binding.E_INVALID),  # mu0 = 0
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], mu0=[1.5]), binding.E_INVALID),       # mu0 > 1
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], mu0=[float("nan")]), binding.E_INVALID),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], mu0=[0.5], flags=8), binding.E_UNSUPPORTED),  # beams + adjoint
+    (dict(N=[8, 8], L=[4, 4], M=[2, 2], n_dphi=[8, 8], mu0=[0.5], below=[1, -1]), binding.E_UNSUPPORTED),
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], mu0=[0.5], base=1), binding.E_UNSUPPORTED),
+    (dict(N=[128], L=[4], M=[2], n_dphi=[8], mu0=[0.5] * 65), binding.E_INVALID),  # above 64 beams
 ])
 def test_plan_validation(kw, code):
     with pytest.raises(binding.VbrdfError) as e:
@@ -94,6 +103,8 @@ def test_null_plan_calls_are_rejected():
     assert lib.vbrdf_solve(None, None, None, None, None, None, None) == binding.E_INVALID
     assert lib.vbrdf_solve_base(None, None, None, None, None, None, None, None) == binding.E_INVALID
     assert lib.vbrdf_plan_base_bytes(None) == 0
+    assert lib.vbrdf_solve_ex(None, None, None, None, None, None, None, None, None) == binding.E_INVALID
+    assert lib.vbrdf_plan_beam_bytes(None) == 0
     assert lib.vbrdf_plan_destroy(None) == binding.OK
     assert lib.vbrdf_plan_output_bytes(None) == 0
     assert lib.vbrdf_stage_name(0).decode() == "validate"
