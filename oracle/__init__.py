@@ -21,6 +21,8 @@ Modules:
   dom         per-order operator, eigen solution, boundary solve, synthesis of F_r
   particular  off-node incidence through the particular solution (eq. 28-33)
   stack       layer stacks (interface continuity, Sec. 2.C) and reflecting bases (eq. 57-66)
+  reconstruct radiance towards arbitrary outgoing directions by source-function integration
+              (eq. 36-38)
   brute       matrix-exponential propagator solve at extended precision (tiny N), also for stacks
               and bases (product of the layers' propagators)
   analytic    single-scattering limit and Chandrasekhar's H-function (isotropic scattering)
