@@ -23,12 +23,23 @@ from .quadrature import double_gauss
 
 
 def _expint(rate, tau0, mu):
-    """int_0^tau0 exp(rate t) exp(-t/mu) dt / mu for complex rates (the limit where they cancel)."""
+    """int_0^tau0 exp(rate t) exp(-t/mu) dt / mu for complex rates with Re(rate) <= 0 (the limit
+    where rate and 1/mu cancel)."""
     a = rate - 1.0 / mu
     small = np.abs(a * tau0) < 1e-8
     safe = np.where(small, 1.0, a)
     val = np.expm1(np.where(small, 0.0, a) * tau0) / (mu * safe)
     return np.where(small, tau0 / mu * (1.0 + 0.5 * a * tau0), val)
+
+
+def _expint_base(rate, tau0, mu):
+    """int_0^tau0 exp(rate (t - tau0)) exp(-t/mu) dt / mu for Re(rate) > 0 (a mode anchored at the
+    base): (exp(-tau0/mu) - exp(-rate tau0)) / (mu (rate - 1/mu)), both exponentials at most 1."""
+    a = rate - 1.0 / mu
+    small = np.abs(a * tau0) < 1e-8
+    safe = np.where(small, 1.0, a)
+    val = (np.exp(-tau0 / mu) - np.exp(-rate * tau0)) / (mu * safe)
+    return np.where(small, tau0 / mu * np.exp(-tau0 / mu) * (1.0 - 0.5 * a * tau0), val)
 
 
 def _field_coefficients(coef, omega, tau0, m, mu, alpha, mu0):
@@ -75,8 +86,8 @@ def solve_order_outgoing(coef, omega, tau0, m, mu, alpha, mu_out, mu0=None):
         rows = 0.5 * omega * Ao.transpose(1, 0, 2).reshape(4, 2 * n) * w[None, :]
         # mode k at depth t: V_k exp(kappa_k t) (decaying, anchored at the top) or
         # V_k exp(kappa_k (t - tau0)) (growing, anchored at the base)
-        f = _expint(kappa, tau0, mo)
-        f = np.where(dec, f, f * np.exp(-kappa * tau0))
+        f = np.where(dec, _expint(np.where(dec, kappa, 0.0), tau0, mo),
+                     _expint_base(np.where(dec, 1.0, kappa), tau0, mo))
         R = (rows @ V) @ (f[:, None] * c)
         if Z is not None:
             Xo = (omega / (2.0 * np.pi)) * phase_fourier_matrix(coef, m, np.array([-mo]), np.array([mu0]))[0, 0]
