@@ -58,36 +58,49 @@ def stage_work(stage, layers):
     return "alu", fl, "TFLOP/s"
 
 
-KERNEL_SOURCE = {"k_eigen": "k_eigen.hip", "k_hqapply": "k_eigen.hip", "k_lu": "k_bc.hip", "k_trsm": "k_bc.hip", "k_vfix": "k_bc.hip",
+KERNEL_SOURCE = {"k_eigen": "k_eigen.hip", "k_eigen_big": "k_eigen.hip", "k_hqapply": "k_eigen.hip", "k_lu": "k_bc.hip", "k_trsm": "k_bc.hip", "k_vfix": "k_bc.hip",
                  "k_bcbuild": "k_bc.hip", "k_colscal": "k_bc.hip", "k_response": "k_bc.hip", "k_gemm": "k_gemm.hip",
                  "k_assemble": "k_assemble.hip", "k_legendre": "k_assemble.hip", "k_validate": "k_assemble.hip",
                  "k_synth": "k_synth.hip", "k_refine": "k_refine.hip"}
 
 
-def stage_kernel(stage):
-    return "k_gemm" if stage.startswith("gemm") else f"k_{stage}"
+def stage_kernels(stage):
+    """Kernels whose launches make up a stage (the eigen stage launches one kernel for the systems
+    held in LDS and one for the larger ones)."""
+    if stage.startswith("gemm"):
+        return ["k_gemm"]
+    if stage == "eigen":
+        return ["k_eigen", "k_eigen_big"]
+    return [f"k_{stage}"]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the recorded byte counters of this workload
-    (profiles/traffic_<workload>.txt), or None when there is no record or the kernel's sources
-    have changed since it was taken."""
+def measured_traffic(kernels, workload):
+    """HBM bytes per launch of the stage made of `kernels`, summed over the kernels recorded in the
+    byte counters of this workload (profiles/traffic_<workload>.txt); None when there is no record
+    or a recorded kernel's sources have changed since it was taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
-    if not os.path.exists(path) or kernel not in KERNEL_SOURCE:
+    if not os.path.exists(path) or any(k not in KERNEL_SOURCE for k in kernels):
         return None
-    h = hashlib.sha256()
-    for part in (KERNEL_SOURCE[kernel], "vbrdf_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1707_05882_amd", "csrc", part), "rb") as fh:
-            h.update(fh.read())
-    sha = h.hexdigest()[:16]
+    rec = {}
     with open(path) as fh:
         for line in fh:
             f = line.split()
-            if len(f) == 5 and f[0] == kernel:
-                return float(f[4]) if f[1] == sha else None
-    return None
+            if len(f) == 5 and f[0] in kernels:
+                rec[f[0]] = (f[1], float(f[4]))
+    if not rec:
+        return None
+    total = 0.0
+    for k, (sha_rec, nbytes) in rec.items():
+        h = hashlib.sha256()
+        for part in (KERNEL_SOURCE[k], "vbrdf_internal.hpp"):
+            with open(os.path.join(ROOT, "paper_1707_05882_amd", "csrc", part), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != sha_rec:
+            return None
+        total += nbytes
+    return total
 
 
 def golden_samples(name):
@@ -335,9 +348,9 @@ def main():
         achieved, peak = work / dur_s / 1e9, PEAK_HBM_GBS
     else:
         achieved, peak = work / dur_s / 1e12, PEAK_FP64_TFLOPS
-    kernel = stage_kernel(dom_stage)
+    kernels = stage_kernels(dom_stage)
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-                "traffic": measured_traffic(kernel, layers.name), "kernel": kernel,
+                "traffic": measured_traffic(kernels, layers.name), "kernel": "+".join(kernels),
                 "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
     one = layers.n_layers == 1
     out = {

@@ -134,6 +134,12 @@ typedef struct vbrdf_plan_desc {
    * 0 = none. Not with stacks, a reflecting base or VBRDF_FLAG_SAVE_FOR_BACKWARD. */
   int32_t n_mu0;
   const double* mu0;
+  /* Extra outgoing directions of the beams (Sec. 2.C "Reconstruction", eq. 36-38): n_mu_out cosines
+   * (host array mu_out[n_mu_out], each in (0, 1], at most 64 and at most N of every layer; needs
+   * n_mu0 > 0) towards which vbrdf_solve_ex also writes the beams' BRDF, by integrating the
+   * source function of the per-order solution along each direction in closed form. 0 = none. */
+  int32_t n_mu_out;
+  const double* mu_out;
 } vbrdf_plan_desc;
 
 /* ABI version of the loaded library (VBRDF_ABI_VERSION). */
@@ -208,16 +214,21 @@ size_t vbrdf_plan_base_bytes(const vbrdf_plan* plan);
 
 /* The general solve: vbrdf_solve_base plus, for a plan with off-node beams (n_mu0 > 0), the BRDF
  * of each beam towards the Gauss nodes:
- *   F_beam    device doubles, per layer [N_out = i][n_mu0 = j][n_dphi = k][4 = r][4 = p], packed
- *             back to back (vbrdf_plan_beam_bytes() bytes): F_r for incidence at mu0_j, outgoing
- *             node i, azimuth difference 2 pi k / n_dphi, referred to the horizontal irradiance
- *             mu0_j I0 as the node table.
+ *   F_beam    device doubles, per layer [N + n_mu_out = i][n_mu0 = j][n_dphi = k][4 = r][4 = p],
+ *             packed back to back (vbrdf_plan_beam_bytes() bytes): F_r for incidence at mu0_j,
+ *             outgoing direction i (the Gauss nodes for i < N, then mu_out[i - N]), azimuth
+ *             difference 2 pi k / n_dphi, referred to the horizontal irradiance mu0_j I0 as the
+ *             node table.
  * Per order the particular solution of the beam's source is found through the eigen-decomposition
  * of the half-size problem, (F E - mu0^-2) G = (F X+ + X- / mu0) M^-1 (eq. 47) solved as
  * U (Lambda - mu0^-2)^-1 U^-1, and the homogeneous part that cancels its incoming diffuse light at
  * the top and the black base comes from the layer's boundary operators. A beam within a relative
  * 1e-12 of a resonance (mu0^-2 equal to an eigenvalue of FE, which in weakly scattering orders
- * happens at the Gauss nodes, where the node table is exact) makes the layer NUMERIC.
+ * happens at the Gauss nodes, where the node table is exact) makes the layer NUMERIC. Towards an
+ * extra outgoing direction the radiance is the source function of eq. 38 (the per-order field at
+ * the nodes, a sum of exponentials in depth, scattered towards -mu, plus the beam's own single
+ * scattering) integrated along the direction in closed form (eq. 37, with the 1/mu its printed form
+ * lacks); at a Gauss node this is the discrete-ordinate value itself.
  * base and the other arguments as for vbrdf_solve_base (base NULL for a black base). vbrdf_solve
  * on a plan with beams computes the node table only. Errors: INVALID (null pointers; F_beam NULL
  * for a plan with beams), as vbrdf_solve. */

@@ -38,12 +38,13 @@ class BRDFSolver:
         self.F_beam = None
         self._beam_views = []
         if self.plan.mu0:
-            nb = len(self.plan.mu0)
+            nb, no = len(self.plan.mu0), len(self.plan.mu_out)
             self.F_beam = torch.empty(self.plan.beam_bytes() // 8, dtype=torch.float64, device=self.device)
             off = 0
             for n, p in zip(self.plan.N, self.plan.n_dphi):
-                self._beam_views.append(self.F_beam[off:off + n * nb * p * 16].view(n, nb, p, 4, 4))
-                off += n * nb * p * 16
+                sz = (n + no) * nb * p * 16
+                self._beam_views.append(self.F_beam[off:off + sz].view(n + no, nb, p, 4, 4))
+                off += sz
 
     def upload(self, tau, omega, coefs):
         dev = self.device
@@ -82,7 +83,8 @@ class BRDFSolver:
         return self._views[i]
 
     def beams(self, i):
-        """(N, n_mu0, n_dphi, 4, 4) view of layer i's off-node beam BRDF (plans built with mu0)."""
+        """(N + n_mu_out, n_mu0, n_dphi, 4, 4) view of layer i's off-node beam BRDF (plans built with
+        mu0): outgoing Gauss nodes first, then the extra outgoing directions mu_out."""
         return self._beam_views[i]
 
 
@@ -171,12 +173,14 @@ _PRECISIONS = {"fp64": binding.PRECISION_FP64, "fp32_refined": binding.PRECISION
 _BASES = {"black": binding.BASE_BLACK, "lambertian": binding.BASE_LAMBERTIAN, "mueller": binding.BASE_MUELLER}
 
 
-def brdf_beam(tau, omega, coef, N, M, n_dphi, mu0, precision="fp64", device="cuda"):
+def brdf_beam(tau, omega, coef, N, M, n_dphi, mu0, mu_out=None, precision="fp64", device="cuda"):
     """BRDF of one layer for incidence at arbitrary cosines mu0 (a sequence, each in (0, 1]) towards
-    the Gauss nodes: a (N, len(mu0), n_dphi, 4, 4) float64 tensor (outgoing node i, incident j,
+    the Gauss nodes and then towards the arbitrary outgoing cosines mu_out: a
+    (N + len(mu_out), len(mu0), n_dphi, 4, 4) float64 tensor (outgoing direction, incident j,
     azimuth difference 2 pi k / n_dphi, Mueller row, column)."""
     L = np.asarray(coef).shape[1]
-    s = BRDFSolver([N], [L], [M], [n_dphi], device=device, precision=_PRECISIONS[precision], mu0=mu0)
+    s = BRDFSolver([N], [L], [M], [n_dphi], device=device, precision=_PRECISIONS[precision], mu0=mu0,
+                   mu_out=mu_out)
     s([tau], [omega], [coef])
     return s.beams(0).clone()
 

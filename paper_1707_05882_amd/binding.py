@@ -81,6 +81,8 @@ class PlanDesc(ctypes.Structure):
         ("base", ctypes.c_int32),
         ("n_mu0", ctypes.c_int32),
         ("mu0", ctypes.POINTER(ctypes.c_double)),
+        ("n_mu_out", ctypes.c_int32),
+        ("mu_out", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -192,7 +194,7 @@ class _Desc:
     """Keeps a PlanDesc and the shape arrays it points to alive together."""
 
     def __init__(self, N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes,
-                 qr_sweep_cap, refine_steps=0, below=None, base=BASE_BLACK, mu0=None):
+                 qr_sweep_cap, refine_steps=0, below=None, base=BASE_BLACK, mu0=None, mu_out=None):
         self.N, self.L, self.M, self.n_dphi = (_as_list(v) for v in (N, L, M, n_dphi))
         nl = len(self.N)
         if not (len(self.L) == len(self.M) == len(self.n_dphi) == nl):
@@ -214,15 +216,25 @@ class _Desc:
             n_mu0 = len(vals)
             m0 = (ctypes.c_double * max(n_mu0, 1))(*vals)
             self.keep.append(m0)
+        mo = None
+        n_mu_out = 0
+        if mu_out is not None:
+            vals = [float(x) for x in np.atleast_1d(mu_out)]
+            n_mu_out = len(vals)
+            mo = (ctypes.c_double * max(n_mu_out, 1))(*vals)
+            self.keep.append(mo)
+        dp = ctypes.POINTER(ctypes.c_double)
         self.desc = PlanDesc(ABI_VERSION, nl, *self.keep[:4], int(precision), int(flags), int(workspace_cap_bytes),
                              ws, int(workspace_bytes), int(qr_sweep_cap), int(refine_steps), bl, int(base),
-                             n_mu0, ctypes.cast(m0, ctypes.POINTER(ctypes.c_double)) if m0 is not None else None)
+                             n_mu0, ctypes.cast(m0, dp) if m0 is not None else None,
+                             n_mu_out, ctypes.cast(mo, dp) if mo is not None else None)
         self.n_layers = nl
 
 
-def workspace_query(N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, below=None, base=BASE_BLACK, mu0=None):
+def workspace_query(N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, below=None, base=BASE_BLACK, mu0=None,
+                    mu_out=None):
     """Bytes of device workspace a plan of these shapes needs (host call)."""
-    d = _Desc(N, L, M, n_dphi, precision, flags, 0, None, 0, 0, 0, below, base, mu0)
+    d = _Desc(N, L, M, n_dphi, precision, flags, 0, None, 0, 0, 0, below, base, mu0, mu_out)
     out = ctypes.c_uint64()
     _check(load().vbrdf_workspace_query(ctypes.byref(d.desc), ctypes.byref(out)))
     return int(out.value)
@@ -233,10 +245,11 @@ class Plan:
 
     def __init__(self, N, L, M, n_dphi, precision=PRECISION_FP64, flags=0, workspace_cap_bytes=0,
                  workspace=None, workspace_bytes=0, qr_sweep_cap=0, refine_steps=0, below=None, base=BASE_BLACK,
-                 mu0=None):
+                 mu0=None, mu_out=None):
         d = _Desc(N, L, M, n_dphi, precision, flags, workspace_cap_bytes, workspace, workspace_bytes, qr_sweep_cap,
-                  refine_steps, below, base, mu0)
+                  refine_steps, below, base, mu0, mu_out)
         self.mu0 = None if mu0 is None else [float(x) for x in np.atleast_1d(mu0)]
+        self.mu_out = [] if mu_out is None else [float(x) for x in np.atleast_1d(mu_out)]
         self.below = None if below is None else [int(b) for b in below]
         self.base = int(base)
         self.N, self.L, self.M, self.n_dphi = d.N, d.L, d.M, d.n_dphi

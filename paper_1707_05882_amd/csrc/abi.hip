@@ -145,6 +145,7 @@ struct vbrdf_plan : LaunchSet {
     if (stack_items_d) (void)hipFree(const_cast<Item*>(stack_items_d));
     if (stack_tasks_d) (void)hipFree(const_cast<StackTask*>(stack_tasks_d));
     if (mu0_d) (void)hipFree(const_cast<double*>(mu0_d));
+    if (mu_out_d) (void)hipFree(const_cast<double*>(mu_out_d));
     if (btasks_d) (void)hipFree(const_cast<BeamTask*>(btasks_d));
   }
 };
@@ -246,6 +247,17 @@ static vbrdf_status check_desc(const vbrdf_plan_desc* d) {
     if (stacks || d->base != VBRDF_BASE_BLACK || (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD))
       return fail(VBRDF_E_UNSUPPORTED, "off-node beams take neither stacks, a reflecting base nor SAVE_FOR_BACKWARD");
   }
+  if (d->n_mu_out < 0 || d->n_mu_out > kMaxBeams)
+    return fail(VBRDF_E_INVALID, "n_mu_out must lie in [0, %d] (got %d)", kMaxBeams, d->n_mu_out);
+  if (d->n_mu_out > 0) {
+    if (d->n_mu0 < 1) return fail(VBRDF_E_INVALID, "extra outgoing directions need off-node beams (n_mu0 > 0)");
+    if (!d->mu_out) return fail(VBRDF_E_INVALID, "null mu_out array");
+    for (int o = 0; o < d->n_mu_out; ++o)
+      if (!(d->mu_out[o] > 0.0 && d->mu_out[o] <= 1.0)) return fail(VBRDF_E_INVALID, "mu_out[%d] outside (0, 1]", o);
+    for (int l = 0; l < d->n_layers; ++l)
+      if (d->n_mu_out > d->N[l])
+        return fail(VBRDF_E_INVALID, "n_mu_out = %d exceeds N = %d of layer %d", d->n_mu_out, d->N[l], l);
+  }
   return VBRDF_OK;
 }
 
@@ -324,8 +336,8 @@ static vbrdf_status build_stacks(vbrdf_plan* p, const vbrdf_plan_desc* d) {
 }
 
 // Per-item workspace blocks, 256-byte aligned.
-static int64_t block_doubles(int N, int L, bool save, int n_mu0) {
-  return n_mu0 > 0 ? block_doubles_beams(4 * N, N, L, n_mu0) : block_doubles_of(4 * N, N, L, save);
+static int64_t block_doubles(int N, int L, bool save, int n_mu0, int n_mu_out) {
+  return n_mu0 > 0 ? block_doubles_beams(4 * N, N, L, n_mu0, n_mu_out) : block_doubles_of(4 * N, N, L, save);
 }
 
 vbrdf_status vbrdf_workspace_query(const vbrdf_plan_desc* d, uint64_t* bytes) {
@@ -335,7 +347,8 @@ vbrdf_status vbrdf_workspace_query(const vbrdf_plan_desc* d, uint64_t* bytes) {
   if (st != VBRDF_OK) return st;
   int64_t total = 0;
   const bool save = (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0;
-  for (int l = 0; l < d->n_layers; ++l) total += (int64_t)d->M[l] * block_doubles(d->N[l], d->L[l], save, d->n_mu0);
+  for (int l = 0; l < d->n_layers; ++l)
+    total += (int64_t)d->M[l] * block_doubles(d->N[l], d->L[l], save, d->n_mu0, d->n_mu_out);
   *bytes = (uint64_t)total * sizeof(double);
   return VBRDF_OK;
 }
@@ -364,8 +377,8 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     ly.quad_off = (int64_t)quad.size();
     ly.item0 = (int64_t)p->items_h.size();
     ly.beam_off = beam_off;
-    beam_off += (int64_t)ly.N * d->n_mu0 * ly.n_dphi * 16;
-    for (int i = 0; i < ly.N; ++i)
+    beam_off += (int64_t)(ly.N + d->n_mu_out) * d->n_mu0 * ly.n_dphi * 16;
+    for (int i = 0; i < ly.N + d->n_mu_out; ++i)
       for (int j = 0; j < d->n_mu0; ++j) btasks.push_back(BeamTask{l, i, j, 0});
     std::vector<double> x, w;
     gauss_legendre(ly.N, x, w);
@@ -380,7 +393,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       it.L = ly.L;
       it.n = n;
       it.ws = ws_off;
-      ws_off += block_doubles(ly.N, ly.L, (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0, d->n_mu0);
+      ws_off += block_doubles(ly.N, ly.L, (d->flags & VBRDF_FLAG_SAVE_FOR_BACKWARD) != 0, d->n_mu0, d->n_mu_out);
       p->items_h.push_back(it);
     }
     for (int i = 0; i < ly.N; ++i)
@@ -512,6 +525,17 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
     if (bs != VBRDF_OK) {
       delete p;
       return bs;
+    }
+    if (d->n_mu_out > 0) {
+      std::vector<double> mo(d->mu_out, d->mu_out + d->n_mu_out);
+      double* mo_d = nullptr;
+      bs = upload(mo, &mo_d);
+      p->mu_out_d = mo_d;
+      if (bs != VBRDF_OK) {
+        delete p;
+        return bs;
+      }
+      p->n_mu_out = d->n_mu_out;
     }
     p->n_mu0 = d->n_mu0;
     p->n_btasks = (int)btasks.size();
@@ -652,6 +676,7 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
     mark();
   }
   if (beams) enqueue_beam_response(*p, tau, layer_status, s);
+  if (beams && p->n_mu_out > 0) enqueue_beam_outgoing(*p, tau, omega, coef, layer_status, s);
   const int rmode = p->stacked ? kResponseBrackets : (p->transmission ? kResponseTransmission : 0);
   k_response<<<dim3(et, et, ni), dim3(16, 16), 0, s>>>(p->items_d, p->layers_d, p->quad_d, p->ws_d, layer_status,
                                                        rmode);

@@ -234,25 +234,28 @@ namespace vbrdf {
 
 // ---- off-node incidence: Legendre table and source at the incident cosines mu0_j
 
-// leg0[(l * n_mu0 + j) * 3 + {0,1,2}] = (Pb, R, T) of order m at mu0_j, as k_legendre at the nodes.
-__global__ __launch_bounds__(kLegThreads) void k_beam_legendre(const Item* items, const double* mu0, int n_mu0,
-                                                               double* ws, const int32_t* status) {
+// Legendre tables of order m at the incident cosines (which = 0: leg0[(l * n_mu0 + j) * 3 + c]) or
+// at the extra outgoing cosines (which = 1: [(l * n_x + o) * 3 + c]), as k_legendre at the nodes.
+__global__ __launch_bounds__(kLegThreads) void k_beam_legendre(const Item* items, const double* xs, int n_x,
+                                                               int n_mu0, int which, double* ws,
+                                                               const int32_t* status) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
   const int L = it.L, m = it.m;
-  double* leg = ws + it.ws + beam_leg_off(it.n, it.N, it.L);
+  double* leg = ws + it.ws + (which ? beam_out_leg_off(it.n, it.N, it.L, n_mu0) : beam_leg_off(it.n, it.N, it.L));
+  const int n_mu0_ = n_x;
   const int seq = threadIdx.x / 128, j = threadIdx.x % 128;
-  if (j < n_mu0) {
-    const double x = mu0[j];
+  if (j < n_mu0_) {
+    const double x = xs[j];
     const int nn = seq == 0 ? 0 : (seq == 1 ? 2 : -2);
     WSeq q{m, nn, seq == 0 ? m : (m > 2 ? m : 2), 0.0, 0.0};
     for (int l = 0; l < L; ++l) {
       const double d = wseq_value(q, l, x);
-      leg[((int64_t)l * n_mu0 + j) * 3 + seq] = (l < m) ? 0.0 : d;
+      leg[((int64_t)l * n_mu0_ + j) * 3 + seq] = (l < m) ? 0.0 : d;
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < L * n_mu0; t += blockDim.x) {
+  for (int t = threadIdx.x; t < L * n_mu0_; t += blockDim.x) {
     double* o = leg + (int64_t)t * 3;
     const double dp = o[1], dm = o[2];
     o[1] = -0.5 * (dp + dm);
@@ -375,6 +378,125 @@ __global__ __launch_bounds__(256) void k_beam_source(const Item* items, const La
       X1[idx] = beam ? sc * sm * inv0 : 0.0;
     }
   }
+}
+
+}  // namespace vbrdf
+
+namespace vbrdf {
+
+// Sums over degrees l of P_l^m(x) B_l P_l^m(y)^T split by parity of l - m into the IQ part and the UV
+// part (as in k_assemble) for one pair of cosines, from Legendre rows li(l) and lj(l).
+struct ParitySums {
+  double q[2][9], u[2][9];
+  __device__ void clear() {
+    for (int e = 0; e < 2; ++e)
+      for (int k = 0; k < 9; ++k) { q[e][k] = 0.0; u[e][k] = 0.0; }
+  }
+  __device__ void add(int e, const double* li, const double* lj, const double* c) {
+    const double pi_ = li[0], ri = li[1], tI = li[2], pj = lj[0], rj = lj[1], tJ = lj[2];
+    const double a1 = c[0], a2 = c[1], a3 = c[2], a4 = c[3], b1 = c[4], b2 = c[5];
+    double* Q = q[e];
+    double* U = u[e];
+    Q[0] += pi_ * a1 * pj; Q[1] += pi_ * b1 * rj; Q[2] += pi_ * b1 * tJ;
+    Q[3] += ri * b1 * pj;  Q[4] += ri * a2 * rj;  Q[5] += ri * a2 * tJ;
+    Q[6] += tI * b1 * pj;  Q[7] += tI * a2 * rj;  Q[8] += tI * a2 * tJ;
+    U[0] += tI * a3 * tJ;  U[1] += tI * a3 * rj;  U[2] += tI * b2 * pj;
+    U[3] += ri * a3 * tJ;  U[4] += ri * a3 * rj;  U[5] += ri * b2 * pj;
+    U[6] += pi_ * b2 * tJ; U[7] += pi_ * b2 * rj; U[8] += pi_ * a4 * pj;
+  }
+  __device__ double iq(int e, int r, int c) const {
+    if (r == 3 || c == 3) return 0.0;
+    const double* Q = q[e];
+    const double v[3][3] = {{Q[0], Q[1], -Q[2]}, {Q[3], Q[4], -Q[5]}, {-Q[6], -Q[7], Q[8]}};
+    return v[r][c];
+  }
+  __device__ double uv(int e, int r, int c) const {
+    if (r == 0 || c == 0) return 0.0;
+    const double* U = u[e];
+    const double v[3][3] = {{U[0], -U[1], -U[2]}, {-U[3], U[4], U[5]}, {U[6], -U[7], U[8]}};
+    return v[r - 1][c - 1];
+  }
+  // A^m(x, y) and A^m(x, -y) D, D = diag(1, 1, -1, -1)
+  __device__ double same(int r, int c) const { return iq(0, r, c) + iq(1, r, c) + uv(0, r, c) + uv(1, r, c); }
+  __device__ double cross(int r, int c) const { return iq(0, r, c) + uv(1, r, c) - uv(0, r, c) - iq(1, r, c); }
+};
+
+// Source rows of the reconstruction (eq. 38) at the extra outgoing cosines mu_o, mirrored storage:
+// kBufB5 = P_cross, kBufB6 = P_same with P_same[(o, r), (j, p)] = omega/2 alpha_j A^m(mu_o, mu_j)[r, p]
+// and P_cross = omega/2 alpha_j [A^m(mu_o, -mu_j) D][r, p]; rows beyond 4 n_out are zeroed. One thread
+// per (o, j) block; grid over (node tiles, outgoing tiles, items).
+__global__ __launch_bounds__(256) void k_recon_rows(const Item* items, const Layer* layers, const double* quad,
+                                                    const double* omega, const double* coef, int n_mu0, int n_out,
+                                                    double* ws, const int32_t* status) {
+  const Item it = items[blockIdx.z];
+  if (status[it.layer] != 0) return;
+  const int N = it.N, L = it.L, m = it.m, n = it.n;
+  const int o = blockIdx.y * 16 + threadIdx.x / 16, j = blockIdx.x * 16 + threadIdx.x % 16;
+  if (o >= N || j >= N) return;
+  double* Pc = buf_ptr(ws, it, kBufB5);
+  double* Ps = buf_ptr(ws, it, kBufB6);
+  if (o >= n_out) {
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        Pc[(int64_t)(4 * o + r) * n + 4 * j + c] = 0.0;
+        Ps[(int64_t)(4 * o + r) * n + 4 * j + c] = 0.0;
+      }
+    return;
+  }
+  const Layer ly = layers[it.layer];
+  const double* leg = ws + it.ws + leg_off(n);
+  const double* lego = ws + it.ws + beam_out_leg_off(n, N, L, n_mu0);
+  const double* cf = coef + ly.coef_off;
+  ParitySums S;
+  S.clear();
+  for (int l = m; l < L; ++l) {
+    const double c6[6] = {cf[l], cf[L + l], cf[2 * L + l], cf[3 * L + l], cf[4 * L + l], cf[5 * L + l]};
+    S.add((l - m) & 1, lego + ((int64_t)l * n_out + o) * 3, leg + ((int64_t)l * N + j) * 3, c6);
+  }
+  const double w = 0.5 * fmin(omega[it.layer], kOmegaMax) * quad[ly.quad_off + N + j];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      const int64_t idx = (int64_t)(4 * o + r) * n + 4 * j + c;
+      Pc[idx] = w * S.cross(r, c);
+      Ps[idx] = w * S.same(r, c);
+    }
+}
+
+// Reconstructed upward radiance at the top towards -mu_o per unit beam e_p at mu0_j (physical
+// storage) into kBufB5: D [Omodes + (P_cross Z+ + P_same D Z- + D X(-mu_o)) f0], with Omodes in
+// kBufB2, the particular part's rows in kBufB7, D X(-mu_o) = omega/(2 pi) A^m(mu_o, -mu0_j) D e_p and
+// f0 = int_0^tau0 exp(-t/mu0) exp(-t/mu_o) dt / mu_o. One thread per (o, j).
+__global__ void k_recon_out(const Item* items, const Layer* layers, const double* omega, const double* coef,
+                            const double* tau, const double* mu0, int n_mu0, const double* mu_out, int n_out,
+                            double* ws, const int32_t* status) {
+  const Item it = items[blockIdx.y];
+  if (status[it.layer] != 0) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_out * n_mu0) return;
+  const int o = t / n_mu0, j = t % n_mu0;
+  const int N = it.N, L = it.L, m = it.m, n = it.n;
+  const Layer ly = layers[it.layer];
+  const double* lego = ws + it.ws + beam_out_leg_off(n, N, L, n_mu0);
+  const double* leg0 = ws + it.ws + beam_leg_off(n, N, L);
+  const double* cf = coef + ly.coef_off;
+  ParitySums S;
+  S.clear();
+  for (int l = m; l < L; ++l) {
+    const double c6[6] = {cf[l], cf[L + l], cf[2 * L + l], cf[3 * L + l], cf[4 * L + l], cf[5 * L + l]};
+    S.add((l - m) & 1, lego + ((int64_t)l * n_out + o) * 3, leg0 + ((int64_t)l * n_mu0 + j) * 3, c6);
+  }
+  const double sc = fmin(omega[it.layer], kOmegaMax) / (2.0 * 3.141592653589793);
+  const double m0 = mu0[j], mo = mu_out[o], tau0 = tau[it.layer];
+  const double f0 = m0 * (-expm1(-tau0 * (1.0 / m0 + 1.0 / mo))) / (m0 + mo);
+  const double* Om = buf_ptr(ws, it, kBufB2);
+  const double* Pz = buf_ptr(ws, it, kBufB7);
+  double* out = buf_ptr(ws, it, kBufB5);
+  for (int r = 0; r < 4; ++r)
+    for (int p = 0; p < 4; ++p) {
+      const int64_t idx = (int64_t)(4 * o + r) * n + 4 * j + p;
+      const double v = Om[idx] + (Pz[idx] + sc * S.cross(r, p)) * f0;
+      out[idx] = r >= 2 ? -v : v;
+    }
 }
 
 }  // namespace vbrdf

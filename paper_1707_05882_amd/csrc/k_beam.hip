@@ -23,7 +23,13 @@
 
 namespace vbrdf {
 
-__global__ void k_beam_legendre(const Item* items, const double* mu0, int n_mu0, double* ws, const int32_t* status);
+__global__ void k_beam_legendre(const Item* items, const double* xs, int n_x, int n_mu0, int which, double* ws,
+                                const int32_t* status);
+__global__ void k_recon_rows(const Item* items, const Layer* layers, const double* quad, const double* omega,
+                             const double* coef, int n_mu0, int n_out, double* ws, const int32_t* status);
+__global__ void k_recon_out(const Item* items, const Layer* layers, const double* omega, const double* coef,
+                            const double* tau, const double* mu0, int n_mu0, const double* mu_out, int n_out,
+                            double* ws, const int32_t* status);
 __global__ void k_beam_source(const Item* items, const Layer* layers, const double* quad, const double* omega,
                               const double* coef, const double* mu0, int n_mu0, double* ws, const int32_t* status);
 
@@ -108,6 +114,8 @@ __global__ void k_beam_resp(const Item* items, const double* tau, const double* 
 
 // F_beam[i][j][k][r][p] = 1/(2 mu0_j) sum_m c_m tau_rp(m dphi_k) R_beam^m[(i, r), 4 j + p]: the
 // synthesis of eq. 12 and 39 with the horizontal irradiance mu0_j I0 (as k_synth for the nodes).
+// Outgoing index i < N: the Gauss nodes (kBufB4); N <= i < N + n_out: the extra outgoing
+// directions (kBufB5, rows 4 (i - N) + r).
 __global__ __launch_bounds__(256) void k_beam_synth(const BeamTask* tasks, const Layer* layers, const Item* items,
                                                     const double* mu0, int n_mu0, const double* ws, double* F,
                                                     const int32_t* status) {
@@ -126,8 +134,9 @@ __global__ __launch_bounds__(256) void k_beam_synth(const BeamTask* tasks, const
   for (int t = tid; t < M * 16; t += NT) {
     const int m = t / 16, rp = t % 16, r = rp / 4, p = rp % 4;
     const Item it = items[ly.item0 + m];
-    const double* B4 = ws + it.ws + bwd_off(n, N, it.L) + (int64_t)(kBufB4 - kNumBuf) * n * n;
-    sR[m][rp] = B4[(int64_t)(4 * tk.i + r) * n + 4 * tk.j + p];
+    const bool node = tk.i < N;
+    const double* B = ws + it.ws + bwd_off(n, N, it.L) + (int64_t)((node ? kBufB4 : kBufB5) - kNumBuf) * n * n;
+    sR[m][rp] = B[(int64_t)(4 * (node ? tk.i : tk.i - N) + r) * n + 4 * tk.j + p];
   }
   for (int t = tid; t < nphi; t += NT) {
     const double a = 6.283185307179586 * (double)t / (double)nphi;
@@ -152,13 +161,212 @@ __global__ __launch_bounds__(256) void k_beam_synth(const BeamTask* tasks, const
   }
 }
 
+// ---- reconstruction towards the extra outgoing cosines (eq. 36-38), half-size form
+//
+// With Phi+- = (u +- nu v) / 2 the homogeneous field is I+(t) = Phi+ A e^(-t/nu) + Phi- B e^(-(tau0-t)/nu)
+// and (mirrored) I-(t) = Phi- A e^(-t/nu) + Phi+ B e^(-(tau0-t)/nu). Its boundary values, the particular
+// solution's incoming light with the sign changed (x_top = -Z+, x_bot = -D Z- exp(-tau0/mu0)), give
+// the mode coefficients through the layer's operators: with E = exp(-tau0/nu),
+//     A + B = 2 (I + E)^-1 U^-1 Y_S (x_top + x_bot),   A - B = 2 (I - E)^-1 U^-1 Y_T (x_top - x_bot).
+// The source of eq. 38 towards -mu (mirrored) is P_cross I+ + P_same I- + D X(-mu) e^(-t/mu0), and each
+// exponential integrates in closed form against exp(-t/mu) dt / mu:
+//     f_A = nu (1 - exp(-tau0 (1/nu + 1/mu))) / (nu + mu),  f_B = nu (exp(-tau0/mu) - exp(-tau0/nu)) / (mu - nu),
+// so the radiance is W_A A + W_B B + (P_cross Z+ + P_same D Z- + D X(-mu)) f0 with the rows
+// W_A = (P_s U + P_d V nu) / 2 f_A, W_B = (P_s U - P_d V nu) / 2 f_B, P_s = P_cross + P_same,
+// P_d = P_cross - P_same. A complex pair (columns k, k+1 holding Re, Im of its eigenvector u) takes
+// the complex scalars nu, f_A, f_B of the eigenvalue with Im > 0: on rows as the column mix
+// (c_k, c_k+1) -> (c_k z_r - c_k+1 z_i, c_k z_i + c_k+1 z_r), on coefficients (which encode
+// (y_k - i y_k+1) / 2) as (y_k, y_k+1) -> (y_k z_r + y_k+1 z_i, -y_k z_i + y_k+1 z_r).
+
+struct Cx2 {
+  double re, im;
+};
+__device__ inline Cx2 cx_mul(Cx2 a, Cx2 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline Cx2 cx_div(Cx2 a, Cx2 b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+__device__ inline Cx2 cx_exp(Cx2 a) {
+  const double e = exp(a.re);
+  return {e * cos(a.im), e * sin(a.im)};
+}
+__device__ inline Cx2 cx_expm1(Cx2 a) {  // e^a - 1, by its series for small |a|
+  if (fabs(a.re) + fabs(a.im) < 1e-4) {
+    const Cx2 a2 = cx_mul(a, a), a3 = cx_mul(a2, a);
+    return {a.re + a2.re / 2 + a3.re / 6, a.im + a2.im / 2 + a3.im / 6};
+  }
+  const Cx2 e = cx_exp(a);
+  return {e.re - 1.0, e.im};
+}
+// nu = lambda^-1/2 with Re nu > 0 for the eigenvalue of column k (the one with Im > 0 for a pair)
+__device__ inline Cx2 mode_nu(const double* lre, const double* lim, int k) {
+  const double a = lre[k], b = lim[k];
+  if (b == 0.0) return {1.0 / sqrt(a), 0.0};
+  const double r = hypot(a, b);
+  const Cx2 sq{sqrt(0.5 * (r + a)), copysign(sqrt(0.5 * (r - a)), b)};  // principal square root
+  return cx_div(Cx2{1.0, 0.0}, sq);
+}
+__device__ inline Cx2 f_a(Cx2 nu, double mu, double tau0) {  // nu (1 - exp(-tau0 (1/nu + 1/mu))) / (nu + mu)
+  const Cx2 inv = cx_div(Cx2{1.0, 0.0}, nu);
+  const Cx2 e = cx_expm1(Cx2{-tau0 * (inv.re + 1.0 / mu), -tau0 * inv.im});
+  return cx_div(cx_mul(nu, Cx2{-e.re, -e.im}), Cx2{nu.re + mu, nu.im});
+}
+__device__ inline Cx2 f_b(Cx2 nu, double mu, double tau0) {
+  // (tau0 / mu) exp(-tau0/mu) expm1(x) / x with x = tau0 (1/mu - 1/nu); directly when |x| is not small
+  const Cx2 inv = cx_div(Cx2{1.0, 0.0}, nu);
+  const Cx2 x{tau0 * (1.0 / mu - inv.re), -tau0 * inv.im};
+  const double em = exp(-tau0 / mu);
+  if (fabs(x.re) + fabs(x.im) < 1e-3) {
+    const Cx2 x2 = cx_mul(x, x), x3 = cx_mul(x2, x);
+    const Cx2 q{1.0 + x.re / 2 + x2.re / 6 + x3.re / 24, x.im / 2 + x2.im / 6 + x3.im / 24};
+    return {tau0 / mu * em * q.re, tau0 / mu * em * q.im};
+  }
+  const Cx2 en = cx_exp(Cx2{-tau0 * inv.re, -tau0 * inv.im});  // exp(-tau0/nu)
+  return cx_div(cx_mul(nu, Cx2{em - en.re, -en.im}), Cx2{mu - nu.re, -nu.im});
+}
+
+// Rows a < 4 n_out: kBufZ = P_s U, kBufX = P_d V on entry; W_A into kBufZ, W_B into kBufX.
+__global__ void k_recon_weights(const Item* items, const double* tau, const double* mu_out, int n_out, double* ws,
+                                const int32_t* status) {
+  const Item it = items[blockIdx.z];
+  if (status[it.layer] != 0) return;
+  const int n = it.n;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = blockIdx.y;
+  if (k >= n || a >= 4 * n_out) return;
+  const double* ex = ws + it.ws + extras_off(n);
+  const double* lre = ex;
+  const double* lim = ex + n;
+  if (lim[k] < 0.0) return;
+  double* WA = buf_ptr(ws, it, kBufZ) + (int64_t)a * n;
+  double* WB = buf_ptr(ws, it, kBufX) + (int64_t)a * n;
+  const double mu = mu_out[a >> 2], tau0 = tau[it.layer];
+  const Cx2 nu = mode_nu(lre, lim, k);
+  const Cx2 fa = f_a(nu, mu, tau0), fb = f_b(nu, mu, tau0);
+  if (lim[k] == 0.0) {
+    const double s = WA[k], d = WB[k] * nu.re;
+    WA[k] = 0.5 * (s + d) * fa.re;
+    WB[k] = 0.5 * (s - d) * fb.re;
+    return;
+  }
+  const double s0 = WA[k], s1 = WA[k + 1], p0 = WB[k], p1 = WB[k + 1];
+  const double d0 = p0 * nu.re - p1 * nu.im, d1 = p0 * nu.im + p1 * nu.re;  // P_d V nu
+  const double a0 = 0.5 * (s0 + d0), a1 = 0.5 * (s1 + d1), b0 = 0.5 * (s0 - d0), b1 = 0.5 * (s1 - d1);
+  WA[k] = a0 * fa.re - a1 * fa.im;
+  WA[k + 1] = a0 * fa.im + a1 * fa.re;
+  WB[k] = b0 * fb.re - b1 * fb.im;
+  WB[k + 1] = b0 * fb.im + b1 * fb.re;
+}
+
+// x_top + x_bot into kBufB2 and x_top - x_bot into kBufB3 (beam columns; zero elsewhere), from
+// kBufB0 = Z+ and kBufB1 = D Z-.
+__global__ void k_recon_x(const Item* items, const double* tau, const double* mu0, int n_mu0, double* ws,
+                          const int32_t* status) {
+  const Item it = items[blockIdx.y];
+  if (status[it.layer] != 0) return;
+  const int n = it.n;
+  const int64_t nn = (int64_t)n * n;
+  const double* Zp = buf_ptr(ws, it, kBufB0);
+  const double* Zm = buf_ptr(ws, it, kBufB1);
+  double* Xs = buf_ptr(ws, it, kBufB2);
+  double* Xd = buf_ptr(ws, it, kBufB3);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nn; t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t % n);
+    if (c >= 4 * n_mu0) {
+      Xs[t] = 0.0;
+      Xd[t] = 0.0;
+      continue;
+    }
+    const double xt = -Zp[t], xb = -Zm[t] * exp(-tau[it.layer] / mu0[c >> 2]);
+    Xs[t] = xt + xb;
+    Xd[t] = xt - xb;
+  }
+}
+
+// Rows c < 4 n_mu0 of kBufF = (U^-1 Y_S x_s)^T and kBufG = (U^-1 Y_T x_d)^T: s = 2 (I + E)^-1 and
+// d = 2 (I - E)^-1 of them, then A = (s + d) / 2 into kBufF and B = (s - d) / 2 into kBufG.
+__global__ void k_recon_coef(const Item* items, const double* tau, int n_mu0, double* ws, const int32_t* status) {
+  const Item it = items[blockIdx.z];
+  if (status[it.layer] != 0) return;
+  const int n = it.n;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (k >= n || c >= 4 * n_mu0) return;
+  const double* ex = ws + it.ws + extras_off(n);
+  const double* lre = ex;
+  const double* lim = ex + n;
+  if (lim[k] < 0.0) return;
+  double* F = buf_ptr(ws, it, kBufF) + (int64_t)c * n;
+  double* G = buf_ptr(ws, it, kBufG) + (int64_t)c * n;
+  const Cx2 nu = mode_nu(lre, lim, k);
+  const Cx2 inv = cx_div(Cx2{1.0, 0.0}, nu);
+  const double tau0 = tau[it.layer];
+  const Cx2 em1 = cx_expm1(Cx2{-tau0 * inv.re, -tau0 * inv.im});   // E - 1
+  const Cx2 ws_ = cx_div(Cx2{2.0, 0.0}, Cx2{2.0 + em1.re, em1.im});  // 2 / (1 + E)
+  const Cx2 wd = cx_div(Cx2{2.0, 0.0}, Cx2{-em1.re, -em1.im});       // 2 / (1 - E)
+  if (lim[k] == 0.0) {
+    const double s = F[k] * ws_.re, d = G[k] * wd.re;
+    F[k] = 0.5 * (s + d);
+    G[k] = 0.5 * (s - d);
+    return;
+  }
+  const double y0 = F[k], y1 = F[k + 1], z0 = G[k], z1 = G[k + 1];
+  const double s0 = y0 * ws_.re + y1 * ws_.im, s1 = -y0 * ws_.im + y1 * ws_.re;
+  const double d0 = z0 * wd.re + z1 * wd.im, d1 = -z0 * wd.im + z1 * wd.re;
+  F[k] = 0.5 * (s0 + d0);
+  F[k + 1] = 0.5 * (s1 + d1);
+  G[k] = 0.5 * (s0 - d0);
+  G[k + 1] = 0.5 * (s1 - d1);
+}
+
+void enqueue_beam_outgoing(const LaunchSet& ls, const double* tau, const double* omega, const double* coef,
+                           int32_t* st, hipStream_t s) {
+  const LaunchSet* p = &ls;
+  const int ni = p->n_items, mn = p->max_n, mN = p->max_N, nb = p->n_mu0, no = p->n_mu_out;
+  const int gt = (mn + 63) / 64, tt = (mn + 31) / 32, at = (mN + 15) / 16;
+  const dim3 gg(gt, gt, ni);
+  auto gemm = [&](int a, int b, int c, int mode) { k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, a, b, c, mode, st); };
+  auto trsm = [&](int a, int rhs, int y) {
+    launch_trsm(p->trsm_rows, dim3(xcd_grid(ni, p->trsm_tiles)), p->trsm_lds, s, p->items_d, ni, p->trsm_tiles,
+                p->ws_d, st, TrsmBufs{{a, a}, {rhs, rhs}, {y, y}, 1, 0});
+  };
+  auto transpose = [&](int a, int b) {
+    k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, a, b, st);
+  };
+  k_beam_legendre<<<ni, kLegThreads, 0, s>>>(p->items_d, p->mu_out_d, no, nb, 1, p->ws_d, st);
+  gemm(kBufE, kBufU, kBufG, 0);  // V = E~ U
+  k_recon_rows<<<dim3(at, at, ni), 256, 0, s>>>(p->items_d, p->layers_d, p->quad_d, omega, coef, nb, no, p->ws_d, st);
+  gemm(kBufB5, kBufB0, kBufB7, 0);
+  gemm(kBufB6, kBufB1, kBufB7, kGemmAccumulate);                // P_cross Z+ + P_same D Z-
+  gemm(kBufB5, kBufU, kBufZ, 0);
+  gemm(kBufB6, kBufU, kBufZ, kGemmAccumulate);                  // P_s U
+  gemm(kBufB5, kBufG, kBufX, 0);
+  gemm(kBufB6, kBufG, kBufX, kGemmNegate | kGemmAccumulate);    // P_d V
+  k_recon_weights<<<dim3((mn + 255) / 256, 4 * no, ni), 256, 0, s>>>(p->items_d, tau, p->mu_out_d, no, p->ws_d, st);
+  k_recon_x<<<dim3(std::min(1024, (mn * mn + 255) / 256), ni), 256, 0, s>>>(p->items_d, tau, p->mu0_d, nb, p->ws_d,
+                                                                            st);
+  gemm(kBufYS, kBufB2, kBufF, 0);                               // Y_S (x_top + x_bot)
+  gemm(kBufYT, kBufB3, kBufG, 0);                               // Y_T (x_top - x_bot)
+  transpose(kBufU, kBufB2);
+  k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, st, LuBufs{{kBufB2, kBufB2}, {kBufB3, kBufB3}, 0});
+  transpose(kBufF, kBufB2);
+  trsm(kBufB3, kBufB2, kBufF);                                  // (U^-1 Y_S x_s)^T
+  transpose(kBufG, kBufB2);
+  trsm(kBufB3, kBufB2, kBufG);                                  // (U^-1 Y_T x_d)^T
+  k_recon_coef<<<dim3((mn + 255) / 256, 4 * nb, ni), 256, 0, s>>>(p->items_d, tau, nb, p->ws_d, st);
+  gemm(kBufZ, kBufF, kBufB2, kGemmTransB);
+  gemm(kBufX, kBufG, kBufB2, kGemmTransB | kGemmAccumulate);    // W_A A + W_B B
+  k_recon_out<<<dim3((no * nb + 63) / 64, ni), 64, 0, s>>>(p->items_d, p->layers_d, omega, coef, tau, p->mu0_d, nb,
+                                                          p->mu_out_d, no, p->ws_d, st);
+}
+
 void enqueue_beam_particular(const LaunchSet& ls, const double* omega, const double* coef, int32_t* st,
                              hipStream_t s) {
   const LaunchSet* p = &ls;
   const int ni = p->n_items, mn = p->max_n, mN = p->max_N, nb = p->n_mu0;
   const int at = (mN + 15) / 16, gt = (mn + 63) / 64, tt = (mn + 31) / 32;
   const dim3 gg(gt, gt, ni);
-  k_beam_legendre<<<ni, kLegThreads, 0, s>>>(p->items_d, p->mu0_d, nb, p->ws_d, st);
+  k_beam_legendre<<<ni, kLegThreads, 0, s>>>(p->items_d, p->mu0_d, nb, nb, 0, p->ws_d, st);
   k_beam_source<<<dim3(at, at, ni), 256, 0, s>>>(p->items_d, p->layers_d, p->quad_d, omega, coef, p->mu0_d, nb,
                                                  p->ws_d, st);
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufB0, kBufB1, kGemmAccumulate, st);  // rhs

@@ -71,18 +71,22 @@ __host__ __device__ inline int64_t bwd_off(int n, int N, int L) { return (item_d
 __host__ __device__ inline int64_t block_doubles_of(int n, int N, int L, bool save) {
   return bwd_off(n, N, L) + (save ? (int64_t)kNumBwdBuf * n * n : 0);
 }
-// Off-node incidence ("beams", a plan option exclusive with the adjoint state): five n x n
-// matrices in the second group's slots, then the Legendre table at the incident cosines
-// [L][n_mu0][3]. The beams of an order occupy the first 4 n_mu0 columns (column 4 j + p: unit
-// Stokes p incident at mu0_j).
-constexpr int kNumBeamBuf = 5;
-enum BeamBuf : int { kBufB0 = kNumBuf, kBufB1, kBufB2, kBufB3, kBufB4 };
+// Off-node incidence ("beams", a plan option exclusive with the adjoint state): eight n x n
+// matrices in the second group's slots, then the Legendre tables at the incident cosines
+// [L][n_mu0][3] and at the extra outgoing cosines [L][n_mu_out][3]. The beams of an order occupy
+// the first 4 n_mu0 columns (column 4 j + p: unit Stokes p incident at mu0_j); the extra outgoing
+// directions the first 4 n_mu_out rows of the reconstruction buffers (row 4 o + r).
+constexpr int kNumBeamBuf = 8;
+enum BeamBuf : int { kBufB0 = kNumBuf, kBufB1, kBufB2, kBufB3, kBufB4, kBufB5, kBufB6, kBufB7 };
 static_assert(kNumBeamBuf <= kNumBwdBuf, "beam buffers use the adjoint's slots");
 __host__ __device__ inline int64_t beam_leg_off(int n, int N, int L) {
   return bwd_off(n, N, L) + (int64_t)kNumBeamBuf * n * n;
 }
-__host__ __device__ inline int64_t block_doubles_beams(int n, int N, int L, int n_mu0) {
-  return (beam_leg_off(n, N, L) + (int64_t)L * n_mu0 * 3 + 31) / 32 * 32;
+__host__ __device__ inline int64_t beam_out_leg_off(int n, int N, int L, int n_mu0) {
+  return beam_leg_off(n, N, L) + (int64_t)L * n_mu0 * 3;
+}
+__host__ __device__ inline int64_t block_doubles_beams(int n, int N, int L, int n_mu0, int n_mu_out) {
+  return (beam_out_leg_off(n, N, L, n_mu0) + (int64_t)L * n_mu_out * 3 + 31) / 32 * 32;
 }
 constexpr int kMaxBeams = 64;  // incident directions per plan
 
@@ -275,6 +279,8 @@ struct LaunchSet {
   // off-node incidence
   int n_mu0 = 0;                            // incident directions (0: none)
   const double* mu0_d = nullptr;            // their cosines
+  int n_mu_out = 0;                         // extra outgoing directions of the beams (0: nodes only)
+  const double* mu_out_d = nullptr;         // their cosines
   const BeamTask* btasks_d = nullptr;       // beam synthesis tasks
   int n_btasks = 0;
 };
@@ -294,6 +300,10 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
 void enqueue_beam_particular(const LaunchSet& ls, const double* omega, const double* coef, int32_t* status,
                              hipStream_t s);
 void enqueue_beam_response(const LaunchSet& ls, const double* tau, int32_t* status, hipStream_t s);
+// the beams' radiance towards the extra outgoing directions by source-function integration (eq. 36-38),
+// after enqueue_beam_response and before the response stage overwrites E~
+void enqueue_beam_outgoing(const LaunchSet& ls, const double* tau, const double* omega, const double* coef,
+                           int32_t* status, hipStream_t s);
 void enqueue_beam_synth(const LaunchSet& ls, double* F_beam, const int32_t* status, hipStream_t s);
 void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omega, const double* dF, double* dtau,
                       double* domega, double* dcoef, hipStream_t s);

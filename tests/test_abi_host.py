@@ -90,6 +90,9 @@ def test_gauss_nodes_rejects_bad_order():
     (dict(N=[8, 8], L=[4, 4], M=[2, 2], n_dphi=[8, 8], mu0=[0.5], below=[1, -1]), binding.E_UNSUPPORTED),
     (dict(N=[8], L=[4], M=[2], n_dphi=[8], mu0=[0.5], base=1), binding.E_UNSUPPORTED),
     (dict(N=[128], L=[4], M=[2], n_dphi=[8], mu0=[0.5] * 65), binding.E_INVALID),  # above 64 beams
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], mu_out=[0.5]), binding.E_INVALID),  # outgoing without beams
+    (dict(N=[8], L=[4], M=[2], n_dphi=[8], mu0=[0.5], mu_out=[0.0]), binding.E_INVALID),
+    (dict(N=[2], L=[4], M=[2], n_dphi=[8], mu0=[0.5], mu_out=[0.1, 0.2, 0.3]), binding.E_INVALID),  # > N
 ])
 def test_plan_validation(kw, code):
     with pytest.raises(binding.VbrdfError) as e:

@@ -114,3 +114,42 @@ def test_node_table_unchanged_by_beams_and_python_entry_point():
     Fx = api.brdf_beam(1.3, 0.95, coef, N, L, P, [0.42, 0.77])
     assert tuple(Fx.shape) == (N, 2, P, 4, 4)
     assert err(Fx[:, 0].cpu().numpy(), particular.brdf_beam(coef, 1.3, 0.95, N, L, P, 0.42)) < TOL
+
+
+def test_outgoing_directions_against_oracle():
+    """Source-function integration (eq. 36-38) towards five arbitrary outgoing cosines, for two
+    beams, against the oracle's reconstruction from the full 8N solution."""
+    from oracle import reconstruct
+
+    N, L, P = 8, 12, 7
+    mu0, mo = [0.3137, 0.8123], [0.07, 0.21, 0.5, 0.83, 0.999]
+    coef, tau, om = hg(340, L), 1.7, 0.93
+    s = BRDFSolver([N], [L], [L], [P], mu0=mu0, mu_out=mo)
+    s([tau], [om], [coef])
+    Fb = s.beams(0).cpu().numpy()
+    assert Fb.shape == (N + len(mo), len(mu0), P, 4, 4)
+    for j, m0 in enumerate(mu0):
+        Fo = reconstruct.brdf_beam_outgoing(coef, tau, om, N, L, P, m0, np.array(mo))
+        assert err(Fb[N:, j], Fo) < TOL, (m0, err(Fb[N:, j], Fo))
+        assert err(Fb[:N, j], particular.brdf_beam(coef, tau, om, N, L, P, m0)) < TOL
+
+
+def test_outgoing_at_full_size_and_at_the_nodes():
+    """N = 32, L = M = n_dphi = 64 (the particulate layer): towards directions placed exactly on
+    Gauss nodes 3 and 17 the reconstruction gives the beams' node rows (the discrete-ordinate values);
+    towards two off-node directions it matches the oracle."""
+    from oracle import reconstruct
+
+    w = workload("particulate")
+    N, L, M, P = w.N[0], w.L[0], w.M[0], w.n_dphi[0]
+    mu, _ = double_gauss(N)
+    mu0 = [0.2371, 0.7519]
+    mo = [mu[3], mu[17], 0.1234, 0.6789]
+    s = BRDFSolver([N], [L], [M], [P], mu0=mu0, mu_out=mo)
+    s([w.tau[0]], [w.omega[0]], [w.coef[0]])
+    Fb = s.beams(0).cpu().numpy()
+    for j in range(len(mu0)):
+        assert err(Fb[N + 0, j], Fb[3, j]) < TOL
+        assert err(Fb[N + 1, j], Fb[17, j]) < TOL
+    Fo = reconstruct.brdf_beam_outgoing(w.coef[0], w.tau[0], w.omega[0], N, M, P, mu0[0], np.array(mo[2:]))
+    assert err(Fb[N + 2:, 0], Fo) < TOL
