@@ -31,31 +31,44 @@ def _operator_mp(coef, omega, m, mu, alpha):
     return K, A, mh
 
 
-def stream_response(coef, omega, tau0, m, N, dps=40):
-    """R^m for unit Stokes inputs on each node (stream form), computed through expm."""
+def _nodes(N, extra):
+    """Gauss nodes followed by extra directions of zero weight: an extra direction is carried
+    through the layer by its own transport equation but adds nothing to the scattering integral,
+    so its upward radiance at the top is the exact formal solution towards it."""
     mu, alpha = double_gauss(N)
-    n = 4 * N
+    extra = np.asarray(extra, dtype=float).reshape(-1)
+    return np.concatenate([mu, extra]), np.concatenate([alpha, np.zeros(len(extra))])
+
+
+def stream_response(coef, omega, tau0, m, N, dps=40, extra=()):
+    """R^m for unit Stokes inputs on each node (stream form), computed through expm.
+
+    Rows: the 4N node rows followed by 4 rows per extra outgoing direction; columns: the 4N node
+    inputs."""
+    mu, alpha = _nodes(N, extra)
+    n = 4 * len(mu)
     with mp.workdps(dps):
         K, _, _ = _operator_mp(coef, omega, m, mu, alpha)
         Psi = mp.expm(K * mp.mpf(tau0))
         Pmm = Psi[n:, n:]
         Pmp = Psi[n:, :n]
         Rop = -(mp.inverse(Pmm) * Pmp)
-        out = np.zeros((n, n))
+        out = np.zeros((n, 4 * N))
         for a in range(n):
-            for b in range(n):
+            for b in range(4 * N):
                 out[a, b] = float(Rop[a, b] / (mp.pi * mp.mpf(alpha[b // 4])))
     return out
 
 
-def beam_response(coef, omega, tau0, m, N, mu0, dps=40):
-    """Reflected diffuse response (4N x 4) to a unit Stokes beam at an off-node mu0.
+def beam_response(coef, omega, tau0, m, N, mu0, dps=40, extra=()):
+    """Reflected diffuse response (4N x 4, then 4 rows per extra outgoing direction) to a unit
+    Stokes beam at an off-node mu0.
 
     The beam enters as the extra state s(tau) = exp(-tau/mu0) of the augmented system
     [[K, Mhat^-1 X], [0, -1/mu0]], X = (omega/2pi) A^m(+-mu_i, mu0) e_p.
     """
-    mu, alpha = double_gauss(N)
-    n = 4 * N
+    mu, alpha = _nodes(N, extra)
+    n = 4 * len(mu)
     mus = np.concatenate([mu, -mu])
     A0 = projected_fourier_matrix(coef, m, mus, np.array([mu0]))[:, 0].reshape(2 * n, 4)
     out = np.zeros((n, 4))

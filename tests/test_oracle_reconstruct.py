@@ -43,3 +43,23 @@ def test_single_scattering_limit_at_arbitrary_angles():
         assert np.abs(F - Fss).max() < om * np.abs(Fss[..., 0, 0]).max()
         rem.append(np.abs(F - Fss).max())
     assert 3.8 < rem[0] / rem[1] < 4.2, rem
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_reconstruction_matches_propagator_with_zero_weight_directions(m):
+    """An outgoing direction carried through the 40-digit propagator as a node of zero weight
+    (its own transport equation, no share in the scattering integral) gives the exact radiance
+    towards it; the source-function integration must agree, for the stream inputs of the nodes and
+    for an off-node beam. No eigenvector, Legendre recurrence or closed-form integral is shared."""
+    from oracle import brute
+
+    N, tau, om, mu0 = 2, 0.9, 0.95, 0.437
+    mo = np.array([0.21, 0.83])
+    coef = hg(7, 6)
+    mu, al = double_gauss(N)
+    Rs = brute.stream_response(coef, om, tau, m, N, dps=30, extra=mo)[4 * N:]
+    Rr = reconstruct.solve_order_outgoing(coef, om, tau, m, mu, al, mo)
+    assert np.abs(Rr - Rs).max() < 1e-11 * np.abs(Rs).max()
+    Rb = brute.beam_response(coef, om, tau, m, N, mu0, dps=30, extra=mo)[4 * N:]
+    Rrb = reconstruct.solve_order_outgoing(coef, om, tau, m, mu, al, mo, mu0)
+    assert np.abs(Rrb - Rb).max() < 1e-11 * np.abs(Rb).max()
