@@ -411,6 +411,223 @@ __device__ void windowed_multibulge(double* __restrict__ H, int n, double* __res
   }
 }
 
+// ---- Blocked Householder reduction to Hessenberg form for systems kept in global memory
+//
+// The step-by-step reduction reads and writes the whole trailing matrix twice per column (left and
+// right update). Here the reflectors of a panel of nb columns are gathered in the compact WY form
+// Q_j = H_0 ... H_{j-1} = I - V T V^T, with W = V T kept instead of T, and the panel's column c is
+// brought up to date on its own: with A_0 the matrix at the panel start and Y = A_0 W,
+//     column c of Q_j^T A_0 Q_j = b - V (W^T b),   b = a0_c - Y V[c, :]^T,
+// on rows p+1..n-1 (the rows a reflector of the panel touches). Each new reflector v_j adds
+//     z = V^T v_j,  W[:, j] = tau (v_j - W z),  Y[:, j] = tau (A_0 v_j - Y z),
+// so the only pass over the matrix inside the panel is the product A_0 v_j (read only). After the
+// panel the trailing columns take the whole transformation at once,
+//     X = A_0 - Y V^T,   X <- X - V (W^T X)   (rows p+1..n-1, columns p+nb..n-1),
+// and the rows above the panel (0..p) take the right update A_0 - (A_0 W) V^T. The reflectors are
+// those of the step-by-step reduction (same v_k, tau_k in QV), up to rounding.
+// Used up to kWinMaxN rows, for the reason given there: at n = 512 the blocked form's rounding
+// moves that node cluster's per-order error past what its refinement absorbs (measured 4.6e-9 of
+// max |R| against about 5e-10 with the step-by-step reduction).
+constexpr int kHessNb = 16;  // panel width: at most 16 (one 32-lane group per dot product)
+constexpr int kHessLds = kWin * kWinLd + kWin * kWinU;  // LDS doubles available (k_eigen_big's buffer)
+
+__device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __restrict__ QV, double* sbuf,
+                                   double* sred) {
+  const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
+  int nb = kHessNb;
+  while (nb > 4 && 3 * nb * n + 2 * n + 64 > kHessLds) nb -= 4;
+  double* Vs = sbuf;          // V[t][a] at Vs[a n + t] (row p + 1 + t)
+  double* Ys = Vs + nb * n;   // Y[t][a] at Ys[a n + t]; after the panel, Y_top[r][a] at Ys[a n + r]
+  double* Ws = Ys + nb * n;   // W[t][a] at Ws[a n + t]
+  double* bs = Ws + nb * n;   // the panel column being reduced
+  double* gs = bs + n;        // A_0 v_j
+  double* us = gs + n;        // W^T b (16), then V^T v_j (16)
+  double* zs = us + 16;
+  const int djj = tid >> 5, dpart = tid & 31;  // 16 dot products, 32 lanes each
+#define AH(r, c) H[(int64_t)(r) * n + (c)]
+  for (int p = 0; p + 2 < n; p += nb) {
+    const int nbp = min(nb, n - 2 - p);
+    const int R = n - p - 1;  // rows p+1..n-1
+    for (int j = 0; j < nbp; ++j) {
+      const int c = p + j;
+      // b = a0_c - Y V[c, :]^T (each thread its own rows t = tid + k NT, as in the Y update below)
+      for (int t = tid; t < R; t += NT) {
+        double x = AH(p + 1 + t, c);
+        for (int a = 0; a < j; ++a) x -= Ys[a * n + t] * Vs[a * n + j - 1];
+        bs[t] = x;
+      }
+      __syncthreads();
+      if (j > 0) {  // u = W^T b
+        double u = 0.0;
+        if (djj < j)
+          for (int t = dpart; t < R; t += 32) u += Ws[djj * n + t] * bs[t];
+        for (int o = 16; o > 0; o >>= 1) u += __shfl_xor(u, o);
+        if (dpart == 0 && djj < j) us[djj] = u;
+        __syncthreads();
+      }
+      // b <- b - V u; the reflector's norm below row c+1
+      double part = 0.0;
+      for (int t = tid; t < R; t += NT) {
+        double x = bs[t];
+        for (int a = 0; a < j; ++a) x -= Vs[a * n + t] * us[a];
+        bs[t] = x;
+        if (t > j) part += x * x;
+      }
+      const double sigma = block_sum(part, sred);
+      const double x0 = bs[j];
+      double tau = 0.0, beta = x0, scal = 0.0;
+      if (sigma != 0.0) {  // uniform
+        const double nrm = sqrt(x0 * x0 + sigma);
+        beta = (x0 >= 0.0) ? -nrm : nrm;
+        tau = (beta - x0) / beta;
+        scal = 1.0 / (x0 - beta);
+      }
+      for (int t = tid; t < R; t += NT) {
+        const double v = (t < j) ? 0.0 : (t == j) ? 1.0 : bs[t] * scal;
+        Vs[j * n + t] = v;
+        if (t >= j) QV[(int64_t)c * n + (t - j)] = v;
+        AH(p + 1 + t, c) = (t < j) ? bs[t] : (t == j) ? beta : 0.0;
+      }
+      if (tid == 0) QV[(int64_t)(n - 1) * n + c] = tau;
+      __syncthreads();
+      // z = V^T v_j (LDS only), then g = A_0 v_j on rows p+1..n-1, columns c+1..n-1
+      if (j > 0) {
+        double z = 0.0;
+        if (djj < j)
+          for (int t = j + dpart; t < R; t += 32) z += Vs[djj * n + t] * Vs[j * n + t];
+        for (int o = 16; o > 0; o >>= 1) z += __shfl_xor(z, o);
+        if (dpart == 0 && djj < j) zs[djj] = z;
+      }
+      for (int rb = wv * 8; rb < R; rb += nw * 8) {
+        double acc[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc[r] = 0.0;
+        for (int col = c + 1 + lane; col < n; col += 64) {
+          const double vv = Vs[j * n + col - p - 1];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) acc[r] += AH(p + 1 + min(rb + r, R - 1), col) * vv;
+        }
+        // 8 sums over 64 lanes: halve the set at each of the first three exchanges
+        {
+          const bool h = lane & 32;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double snd = h ? acc[r] : acc[r + 4], kp = h ? acc[r + 4] : acc[r];
+            acc[r] = kp + __shfl_xor(snd, 32);
+          }
+        }
+        {
+          const bool h = lane & 16;
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            const double snd = h ? acc[r] : acc[r + 2], kp = h ? acc[r + 2] : acc[r];
+            acc[r] = kp + __shfl_xor(snd, 16);
+          }
+        }
+        {
+          const bool h = lane & 8;
+          const double snd = h ? acc[0] : acc[1], kp = h ? acc[1] : acc[0];
+          acc[0] = kp + __shfl_xor(snd, 8);
+        }
+        acc[0] += __shfl_xor(acc[0], 4);
+        acc[0] += __shfl_xor(acc[0], 2);
+        acc[0] += __shfl_xor(acc[0], 1);
+        const int row = rb + ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
+        if ((lane & 7) == 0 && row < R) gs[row] = acc[0];
+      }
+      __syncthreads();
+      // W[:, j] = tau (v_j - W z), Y[:, j] = tau (g - Y z); the next column's update reads only
+      // the rows each thread writes here, so no barrier follows
+      for (int t = tid; t < R; t += NT) {
+        double wy = Vs[j * n + t], yy = gs[t];
+        for (int a = 0; a < j; ++a) {
+          wy -= Ws[a * n + t] * zs[a];
+          yy -= Ys[a * n + t] * zs[a];
+        }
+        Ws[j * n + t] = tau * wy;
+        Ys[j * n + t] = tau * yy;
+      }
+    }
+    __syncthreads();
+    // trailing columns p+nbp..n-1 on rows p+1..n-1: X = A_0 - Y V^T, X <- X - V (W^T X).
+    // Lane = 16 columns x 4 row parts; a wave covers 16 columns, its 4 parts combine W^T X.
+    {
+      const int ci = lane & 15, rp = lane >> 4;
+      for (int cb = p + nbp + 16 * wv; cb < n; cb += 16 * nw) {
+        const int col = min(cb + ci, n - 1);
+        const bool live = cb + ci < n;
+        double vc[kHessNb], acc[kHessNb];
+#pragma unroll
+        for (int a = 0; a < kHessNb; ++a) {
+          vc[a] = (a < nbp) ? Vs[a * n + col - p - 1] : 0.0;
+          acc[a] = 0.0;
+        }
+        for (int t = rp; t < R; t += 4) {
+          double x = AH(p + 1 + t, col);
+#pragma unroll
+          for (int a = 0; a < kHessNb; ++a)
+            if (a < nbp) x -= Ys[a * n + t] * vc[a];
+#pragma unroll
+          for (int a = 0; a < kHessNb; ++a)
+            if (a < nbp) acc[a] += Ws[a * n + t] * x;
+        }
+#pragma unroll
+        for (int a = 0; a < kHessNb; ++a) {
+          acc[a] += __shfl_xor(acc[a], 16);
+          acc[a] += __shfl_xor(acc[a], 32);
+        }
+        for (int t = rp; t < R; t += 4) {
+          double x = AH(p + 1 + t, col);
+#pragma unroll
+          for (int a = 0; a < kHessNb; ++a)
+            if (a < nbp) x -= Ys[a * n + t] * vc[a] + Vs[a * n + t] * acc[a];
+          if (live) AH(p + 1 + t, col) = x;
+        }
+      }
+    }
+    __syncthreads();
+    // rows 0..p, columns p+1..n-1: Y_top = A_0 W (lane = 16 columns x 4 rows), then A_0 - Y_top V^T
+    {
+      const int ci = lane & 15, rq = lane >> 4;
+      for (int rb = 4 * wv; rb <= p; rb += 4 * nw) {
+        const int r = min(rb + rq, p);
+        double acc[kHessNb];
+#pragma unroll
+        for (int a = 0; a < kHessNb; ++a) acc[a] = 0.0;
+        for (int t = ci; t < R; t += 16) {
+          const double x = AH(r, p + 1 + t);
+#pragma unroll
+          for (int a = 0; a < kHessNb; ++a)
+            if (a < nbp) acc[a] += x * Ws[a * n + t];
+        }
+#pragma unroll
+        for (int a = 0; a < kHessNb; ++a)
+          for (int o = 8; o > 0; o >>= 1) acc[a] += __shfl_xor(acc[a], o);
+        if (ci == 0 && rb + rq <= p)
+#pragma unroll
+          for (int a = 0; a < kHessNb; ++a)
+            if (a < nbp) Ys[a * n + r] = acc[a];
+      }
+      __syncthreads();
+      for (int t = tid; t < R; t += NT) {  // lanes along columns, each thread all rows 0..p
+        const int col = p + 1 + t;
+        double vc[kHessNb];
+#pragma unroll
+        for (int a = 0; a < kHessNb; ++a) vc[a] = (a < nbp) ? Vs[a * n + t] : 0.0;
+        for (int r = 0; r <= p; ++r) {
+          double x = AH(r, col);
+#pragma unroll
+          for (int a = 0; a < kHessNb; ++a)
+            if (a < nbp) x -= Ys[a * n + r] * vc[a];
+          AH(r, col) = x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#undef AH
+}
+
 template <bool kLds>
 __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t* status, double* sH, double* srefl,
                                            double* sred, int* sctl, double* sxyz, ZOp* zops, int sweep_cap) {
@@ -460,81 +677,86 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
   // QR phase starts from Z = I. Each dot product of the two-sided update is split over P adjacent
   // lanes (combined by lane exchange) so that all threads work although a step has at most n
   // columns and n rows. The column below the subdiagonal is kept raw in sv (v_0 = 1 and
-  // v_i = sv[i] / (x0 - beta)), which lets its norm and its copy share one barrier.
+  // v_i = sv[i] / (x0 - beta)), which lets its norm and its copy share one barrier. Systems kept
+  // in global memory take the blocked form (blocked_hessenberg), which produces the same reflectors.
   double* __restrict__ QV = base + (int64_t)kBufYS * n * n;  // v_k at QV[k n + i], tau_k at QV[(n-1) n + k]
-  int Pr = 1;
-  while (Pr < 4 && n * Pr * 2 <= NT) Pr *= 2;
-  const int line_r = hess_line(tid, Pr, NT);
-  for (int k = 0; k + 2 < n; ++k) {
-    const int len = n - k - 1;
-    double part = 0.0;
-    for (int i = 1 + tid; i < len; i += NT) {
-      const double v = HH(k + 1 + i, k);
-      sv[i] = v;
-      part += v * v;
-    }
-    const double x0 = HH(k + 1, k);
-    part = wave_sum(part);
-    double* red = sred + 8 * (k & 1);  // two reduction slots: no second barrier needed
-    if ((tid & 63) == 0) red[tid >> 6] = part;
-    __syncthreads();
-    double sigma = 0.0;
-    for (int w = 0; w < (NT + 63) / 64; ++w) sigma += red[w];
-    if (sigma == 0.0) {  // column already reduced (uniform decision)
-      if (tid == 0) QV[(int64_t)(n - 1) * n + k] = 0.0;
-      continue;
-    }
-    const double nrm = sqrt(x0 * x0 + sigma);
-    const double beta = (x0 >= 0.0) ? -nrm : nrm;
-    const double tau = (beta - x0) / beta;
-    const double dlt = x0 - beta;
-    const double scal = 1.0 / dlt;
-    for (int i = tid; i < len; i += NT) {
-      QV[(int64_t)k * n + i] = (i == 0) ? 1.0 : sv[i] * scal;
-      HH(k + 1 + i, k) = (i == 0) ? beta : 0.0;
-    }
-    if (tid == 0) QV[(int64_t)(n - 1) * n + k] = tau;
-    // left: (I - tau v v^T) H on columns k+1..n-1
-    int Pl = 1;
-    while (Pl < 8 && len * Pl * 2 <= NT) Pl *= 2;
-    const int part_l = tid & (Pl - 1);
-    const int line_l = hess_line(tid, Pl, NT);
-    for (int c0 = k + 1; c0 < n; c0 += NT / Pl) {
-      const int c = c0 + line_l;
-      double w = 0.0;
-      if (c < n) {
-        if (part_l == 0) w = HH(k + 1, c) * dlt;
-#pragma unroll 4
-        for (int i = (part_l == 0 ? Pl : part_l); i < len; i += Pl) w += sv[i] * HH(k + 1 + i, c);
+  if (!kLds && n <= kWinMaxN) {
+    blocked_hessenberg(H, n, QV, sH, sred);
+  } else {
+    int Pr = 1;
+    while (Pr < 4 && n * Pr * 2 <= NT) Pr *= 2;
+    const int line_r = hess_line(tid, Pr, NT);
+    for (int k = 0; k + 2 < n; ++k) {
+      const int len = n - k - 1;
+      double part = 0.0;
+      for (int i = 1 + tid; i < len; i += NT) {
+        const double v = HH(k + 1 + i, k);
+        sv[i] = v;
+        part += v * v;
       }
-      for (int o = 1; o < Pl; o <<= 1) w += __shfl_xor(w, o);
-      w *= tau * scal;
-      if (c < n) {
-        if (part_l == 0) HH(k + 1, c) -= w;
-#pragma unroll 4
-        for (int i = (part_l == 0 ? Pl : part_l); i < len; i += Pl) HH(k + 1 + i, c) -= sv[i] * scal * w;
+      const double x0 = HH(k + 1, k);
+      part = wave_sum(part);
+      double* red = sred + 8 * (k & 1);  // two reduction slots: no second barrier needed
+      if ((tid & 63) == 0) red[tid >> 6] = part;
+      __syncthreads();
+      double sigma = 0.0;
+      for (int w = 0; w < (NT + 63) / 64; ++w) sigma += red[w];
+      if (sigma == 0.0) {  // column already reduced (uniform decision)
+        if (tid == 0) QV[(int64_t)(n - 1) * n + k] = 0.0;
+        continue;
       }
+      const double nrm = sqrt(x0 * x0 + sigma);
+      const double beta = (x0 >= 0.0) ? -nrm : nrm;
+      const double tau = (beta - x0) / beta;
+      const double dlt = x0 - beta;
+      const double scal = 1.0 / dlt;
+      for (int i = tid; i < len; i += NT) {
+        QV[(int64_t)k * n + i] = (i == 0) ? 1.0 : sv[i] * scal;
+        HH(k + 1 + i, k) = (i == 0) ? beta : 0.0;
+      }
+      if (tid == 0) QV[(int64_t)(n - 1) * n + k] = tau;
+      // left: (I - tau v v^T) H on columns k+1..n-1
+      int Pl = 1;
+      while (Pl < 8 && len * Pl * 2 <= NT) Pl *= 2;
+      const int part_l = tid & (Pl - 1);
+      const int line_l = hess_line(tid, Pl, NT);
+      for (int c0 = k + 1; c0 < n; c0 += NT / Pl) {
+        const int c = c0 + line_l;
+        double w = 0.0;
+        if (c < n) {
+          if (part_l == 0) w = HH(k + 1, c) * dlt;
+  #pragma unroll 4
+          for (int i = (part_l == 0 ? Pl : part_l); i < len; i += Pl) w += sv[i] * HH(k + 1 + i, c);
+        }
+        for (int o = 1; o < Pl; o <<= 1) w += __shfl_xor(w, o);
+        w *= tau * scal;
+        if (c < n) {
+          if (part_l == 0) HH(k + 1, c) -= w;
+  #pragma unroll 4
+          for (int i = (part_l == 0 ? Pl : part_l); i < len; i += Pl) HH(k + 1 + i, c) -= sv[i] * scal * w;
+        }
+      }
+      __syncthreads();
+      // right: H (I - tau v v^T), rows 0..n-1
+      const int part_r = tid & (Pr - 1);
+      for (int r0 = 0; r0 < n; r0 += NT / Pr) {
+        const int r = r0 + line_r;
+        double y = 0.0;
+        if (r < n) {
+          if (part_r == 0) y = HH(r, k + 1);
+  #pragma unroll 4
+          for (int i = (part_r == 0 ? Pr : part_r); i < len; i += Pr) y += HH(r, k + 1 + i) * (sv[i] * scal);
+        }
+        for (int o = 1; o < Pr; o <<= 1) y += __shfl_xor(y, o);
+        y *= tau;
+        if (r < n) {
+          if (part_r == 0) HH(r, k + 1) -= y;
+  #pragma unroll 4
+          for (int i = (part_r == 0 ? Pr : part_r); i < len; i += Pr) HH(r, k + 1 + i) -= y * (sv[i] * scal);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // right: H (I - tau v v^T), rows 0..n-1
-    const int part_r = tid & (Pr - 1);
-    for (int r0 = 0; r0 < n; r0 += NT / Pr) {
-      const int r = r0 + line_r;
-      double y = 0.0;
-      if (r < n) {
-        if (part_r == 0) y = HH(r, k + 1);
-#pragma unroll 4
-        for (int i = (part_r == 0 ? Pr : part_r); i < len; i += Pr) y += HH(r, k + 1 + i) * (sv[i] * scal);
-      }
-      for (int o = 1; o < Pr; o <<= 1) y += __shfl_xor(y, o);
-      y *= tau;
-      if (r < n) {
-        if (part_r == 0) HH(r, k + 1) -= y;
-#pragma unroll 4
-        for (int i = (part_r == 0 ? Pr : part_r); i < len; i += Pr) HH(r, k + 1 + i) -= y * (sv[i] * scal);
-      }
-    }
-    __syncthreads();
   }
 
   // ---- 2. Francis double-shift QR to real Schur form
