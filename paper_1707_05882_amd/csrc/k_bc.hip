@@ -211,7 +211,161 @@ __device__ __forceinline__ bool lu_factor(T* A, int64_t ld, int n, int* perm, T*
   return true;
 }
 
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// Blocked form of lu_factor for systems kept in global memory (same conventions: logical row
+// exchanges through perm, L and Uu in place, invd = 1 / Uu_kk, pivot = largest modulus with ties
+// to the smaller position). The rank-1 updates of the step-by-step form read and write the whole
+// trailing matrix once per column; here a panel of kLuNb columns is factored in LDS, the panel's
+// rows of Uu to its right follow from a unit-triangular solve (L11 U12 = A12), and the trailing
+// matrix takes the panel's whole update A22 -= L21 U12 at once, on the matrix cores
+// (v_mfma_f64_16x16x4, rows addressed through the pivot order). P: LDS of at least
+// (n + 1) kLuNb doubles; sL: kLuNb (kLuNb + 1) doubles (L11 at a fixed stride with zeros on and
+// above the diagonal, so that the forward substitution needs no predicate and addresses it by
+// immediate offsets); rv, ri: 32 doubles and 16 ints of LDS. The block
+// is 1024 threads.
+constexpr int kLuNb = 32;
+static_assert(kLuNb % 4 == 0 && kLuNb <= 64, "panel width: whole MFMA k-steps");
+
+__device__ bool lu_blocked(double* __restrict__ A, int n, int* perm, double* invd, double* P, double* sL, double* rv,
+                           int* ri) {
+  const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
+  for (int i = tid; i < n; i += NT) perm[i] = i;
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += kLuNb) {
+    const int w = min(kLuNb, n - k0), m = n - k0;
+    const int ldp = m | 1;  // odd stride: a row of the panel spreads over the LDS banks
+    // panel P[q][i] = A(perm[k0 + i], k0 + q): 32 lanes along a row's panel columns
+    for (int t = tid; t < m * kLuNb; t += NT) {
+      const int i = t / kLuNb, q = t % kLuNb;
+      if (q < w) P[q * ldp + i] = A[(int64_t)perm[k0 + i] * n + k0 + q];
+    }
+    __syncthreads();
+    for (int q = 0; q < w; ++q) {
+      // pivot: largest |P[q][i]| over i >= q, ties to the smaller position
+      const int i = q + tid;
+      double best = -1.0, bval = 0.0;
+      int bi = m;
+      if (i < m) {
+        bval = P[q * ldp + i];
+        best = fabs(bval);
+        bi = i;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o), ov = __shfl_xor(bval, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bval = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        rv[wv] = best;
+        rv[16 + wv] = bval;
+        ri[wv] = bi;
+      }
+      __syncthreads();
+      best = rv[0];
+      bval = rv[16];
+      bi = ri[0];
+      for (int v = 1; v < nw; ++v)
+        if (rv[v] > best || (rv[v] == best && ri[v] < bi)) {
+          best = rv[v];
+          bval = rv[16 + v];
+          bi = ri[v];
+        }
+      if (!(best > 0.0 && isfinite(best))) return false;  // uniform
+      const double inv = 1.0 / bval;
+      __syncthreads();  // every thread has read rv, ri
+      if (bi != q) {
+        if (tid < w) {
+          const double x = P[tid * ldp + q];
+          P[tid * ldp + q] = P[tid * ldp + bi];
+          P[tid * ldp + bi] = x;
+        }
+        if (tid == 0) {
+          const int x = perm[k0 + q];
+          perm[k0 + q] = perm[k0 + bi];
+          perm[k0 + bi] = x;
+        }
+      }
+      if (tid == 0) invd[k0 + q] = inv;
+      __syncthreads();
+      // scale the column below the pivot and update the panel columns to its right (row per thread)
+      if (i > q && i < m) {
+        const double l = P[q * ldp + i] * inv;
+        P[q * ldp + i] = l;
+        for (int c = q + 1; c < w; ++c) P[c * ldp + i] -= l * P[c * ldp + q];
+      }
+      __syncthreads();
+    }
+    // panel back to global memory under the new order
+    for (int t = tid; t < m * kLuNb; t += NT) {
+      const int i = t / kLuNb, q = t % kLuNb;
+      if (q < w) A[(int64_t)perm[k0 + i] * n + k0 + q] = P[q * ldp + i];
+    }
+    const int r0 = k0 + w;
+    if (r0 >= n) break;  // from here on the panel is whole: w = kLuNb
+    for (int t = tid; t < kLuNb * kLuNb; t += NT) {  // strictly lower part of L11, zeros elsewhere
+      const int sc = t / kLuNb, r = t % kLuNb;
+      sL[sc * (kLuNb + 1) + r] = r > sc ? P[sc * ldp + r] : 0.0;
+    }
+    __syncthreads();
+    // A wave per block of 16 columns to the right of the panel: first U12 = L11^-1 A12 for those
+    // columns by forward substitution, held in the B-operand layout of v_mfma_f64_16x16x4
+    // (x[t] = row 4 t + lane / 16, column lane % 16; row s comes from its lane by an exchange),
+    // then A22 -= L21 U12 in 16 x 16 tiles, A = -L21 from the LDS panel, the accumulator starting
+    // from the tile of A22.
+    {
+      const int lr = lane & 15, kq = lane >> 4;
+      const int nrest = n - r0;
+      for (int cb = wv; cb * 16 < nrest; cb += nw) {
+        const int col = r0 + cb * 16 + lr;
+        const bool live = col < n;
+        const int colc = live ? col : n - 1;
+        double x[kLuNb / 4];
+#pragma unroll
+        for (int t = 0; t < kLuNb / 4; ++t) x[t] = A[(int64_t)perm[k0 + 4 * t + kq] * n + colc];
+#pragma unroll
+        for (int sr = 0; sr + 1 < kLuNb; ++sr) {
+          const double xs = __shfl(x[sr >> 2], ((sr & 3) << 4) | lr);
+#pragma unroll
+          for (int t = sr >> 2; t < kLuNb / 4; ++t)
+            x[t] -= sL[sr * (kLuNb + 1) + 4 * t + kq] * xs;
+          __builtin_amdgcn_sched_barrier(0);  // keep each step's loads in their step (registers)
+        }
+        if (live)
+#pragma unroll
+          for (int t = 0; t < kLuNb / 4; ++t) A[(int64_t)perm[k0 + 4 * t + kq] * n + col] = x[t];
+        for (int rb = 0; rb * 16 < nrest; ++rb) {
+          double4_t acc;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int pos = r0 + rb * 16 + kq + 4 * v;
+            acc[v] = (pos < n && live) ? A[(int64_t)perm[pos] * n + col] : 0.0;
+          }
+          const int pi = w + rb * 16 + lr;  // panel row of the A operand
+#pragma unroll
+          for (int t = 0; t < kLuNb / 4; ++t) {
+            const double a = pi < m ? -P[(4 * t + kq) * ldp + pi] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, x[t], acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int pos = r0 + rb * 16 + kq + 4 * v;
+            if (pos < n && live) A[(int64_t)perm[pos] * n + col] = acc[v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
 constexpr int kLuLds = kLdsMaxn * (kLdsMaxn + 1);  // LDS matrix
+static_assert(kLuLds >= (kMaxn + 1) * kLuNb, "the panel of the blocked factorisation fits");
 constexpr int kVfixLds = kLuLds + kLdsMaxn;          // LDS matrix and one work vector
 static_assert(kVfixLds >= 2 * 256, "the column-maximum partials of a 256-thread block fit");
 
@@ -226,7 +380,7 @@ __device__ inline int* lu_perm(double* ex, int n, int which) {
 // boundary solve, or U^T of the eigenpair refinement), P^T A = L Uu. The factor is written
 // transposed into b.dst[side], AT[j n + c] = A(c, j), so that column j of Uu (c < j) and of L
 // (c > j) are contiguous for the right division; pivots and 1 / Uu_kk go to the extras block.
-// The source buffer is overwritten when n > kLdsMaxn (factored in place).
+// The source buffer is overwritten when n > kLdsMaxn (factored in place, in blocked form).
 __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
@@ -241,6 +395,9 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
   __shared__ int perm[2 * kMaxn];
   __shared__ double invd[kMaxn];
   __shared__ int redi[8];
+  __shared__ double slu_rv[32];
+  __shared__ double slu_l[kLuNb * (kLuNb + 1)];
+  __shared__ int slu_ri[16];
   const bool in_lds = n <= kLdsMaxn;
   double* A = in_lds ? smem : Ag;
   const int64_t ld = in_lds ? n + 1 : n;
@@ -250,7 +407,7 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
     __syncthreads();
     ok = lu_factor<kLdsMaxn / 64>(smem, n + 1, n, perm, invd, redi);
   } else {
-    ok = lu_factor<kMaxn / 64>(Ag, n, n, perm, invd, redi);
+    ok = lu_blocked(Ag, n, perm, invd, smem, slu_l, slu_rv, slu_ri);
   }
   if (!ok) {
     if (tid == 0) status[it.layer] = -5;
