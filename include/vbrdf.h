@@ -288,7 +288,9 @@ vbrdf_status vbrdf_backward(vbrdf_plan* plan, const double* tau, const double* o
                                        largest first, until none is left */
 typedef struct vbrdf_tuning {
   int32_t eigen_schedule; /* VBRDF_EIGEN_* */
-  int32_t trsm_rows;      /* 4, 8 (default) or 16 right-hand-side rows per right-division tile */
+  int32_t trsm_rows;      /* 4, 8 or 16 (default) right-hand-side rows per right-division tile; 4 and 8
+                             split each dot product over the lanes of one wave, 16 runs the blocked
+                             solve on the matrix cores */
 } vbrdf_tuning;
 
 /* Current choices of the plan (host call). */

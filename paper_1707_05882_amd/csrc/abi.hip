@@ -490,7 +490,7 @@ vbrdf_status vbrdf_plan_create(const vbrdf_plan_desc* d, vbrdf_plan** out) {
       }
     }
   }
-  set_trsm_rows(p, kTrsmRows);
+  set_trsm_rows(p, kTrsmRowsDefault);
   for (int rows : {4, 8, 16}) {
     const size_t lds = trsm_lds_for(p->max_n, rows);
     if (lds <= 65536) continue;  // the right-division tile of a large system exceeds the default LDS cap

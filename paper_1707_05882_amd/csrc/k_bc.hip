@@ -531,6 +531,146 @@ __device__ __forceinline__ void trsm_tile(const Item& it, int which, int r0, dou
   }
 }
 
+// Right division Y = B A^-1 for a tile of 16 rows of B on the matrix cores (the kRows = 16 form of
+// k_trsm; same factors, pivots and output convention as trsm_tile). One wave. The tile is kept in
+// LDS column by column, Zt[c][r] (stride 17). Both triangular solves go by blocks of 16 columns:
+//   Z Uu = B  (ascending):  Z_J = (B_J - Z_{<J} Uu_{<J,J}) Uu_JJ^-1,
+//   W L = Z   (descending): W_J = Z_J - W_{>J} L_{>J,J}         (unit diagonal),
+// the products with v_mfma_f64_16x16x4 (A = -Z or -W from LDS: row = lane % 16, k = lane / 16 +
+// 4 t; B = the factor's columns, read from AT where they are contiguous; two accumulators so that
+// consecutive MFMAs do not wait on each other), the 16 x 16 diagonal blocks by substitution in the
+// accumulator layout (row lane / 16 + 4 v, column lane % 16), column c handed to the other lanes
+// by an exchange.
+constexpr int kTrsmLdz = 17;
+
+// acc -= Zt[:, kb:ke] F[kb:ke, col] for the 16 rows of the tile (ke - kb a multiple of 4; fc a valid
+// column of the factor also for padding lanes, whose results are discarded): chunks of 8 k-steps
+// whose factor loads are issued one chunk ahead. Loads are unconditional (indices clamped) and the
+// k-steps past ke get a zero A operand, so the code has no branches between a load and its use and
+// the next chunk's loads stay in flight over the current chunk's MFMAs.
+__device__ __forceinline__ void trsm_block_product(const double* Zt, const double* __restrict__ fc, int n, int kb,
+                                                   int ke, int lr, int kq, double4_t& acc0, double4_t& acc1) {
+  constexpr int kC = 8;
+  double bc[kC], bn[kC];
+#pragma unroll
+  for (int u = 0; u < kC; ++u) bc[u] = fc[min(kb + 4 * u + kq, n - 1)];
+  for (int k = kb; k < ke; k += 4 * kC) {
+#pragma unroll
+    for (int u = 0; u < kC; ++u) bn[u] = fc[min(k + 4 * kC + 4 * u + kq, n - 1)];
+    double a[kC];
+#pragma unroll
+    for (int u = 0; u < kC; ++u) {
+      const double z = Zt[min(k + 4 * u + kq, n - 1) * kTrsmLdz + lr];
+      a[u] = (k + 4 * u < ke) ? -z : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kC; u += 2) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bc[u], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u + 1], bc[u + 1], acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kC; ++u) bc[u] = bn[u];
+  }
+}
+
+__device__ __forceinline__ void trsm_tile_mfma(const Item& it, int which, int r0, double* ws,
+                                               const double* __restrict__ AT, const double* __restrict__ U,
+                                               double* __restrict__ Y) {
+  const int n = it.n, lane = threadIdx.x;
+  const int lr = lane & 15, kq = lane >> 4;
+  double* base = ws + it.ws;
+  double* ex = base + extras_off(n);
+  const double* __restrict__ id = lu_invd(ex, n, which);
+  const int* __restrict__ pm = lu_perm(ex, n, which);
+  HIP_DYNAMIC_SHARED(double, Zt)
+  const int nr = min(16, n - r0);
+  // the tile's rows, 8 loads in flight per lane
+  for (int t0 = 0; t0 < 16 * n; t0 += 8 * 64) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = min(t0 + 64 * u + lane, 16 * n - 1), rr = t / n;
+      v[u] = U[(int64_t)min(r0 + rr, n - 1) * n + t % n];
+      if (rr >= nr) v[u] = 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + 64 * u + lane;
+      if (t < 16 * n) Zt[(t % n) * kTrsmLdz + t / n] = v[u];
+    }
+  }
+  auto sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+  sync();
+  const int nblk = (n + 15) >> 4;
+  // Z Uu = B
+  for (int jb = 0; jb < nblk; ++jb) {
+    const int j0 = jb * 16, col = j0 + lr, nv = min(16, n - j0);
+    const bool cl = col < n;
+    const double* __restrict__ fc = AT + (int64_t)(cl ? col : 0) * n;  // column col of the factor
+    // the diagonal block's factor entries and this column's 1 / Uu_jj, loaded ahead of the product
+    double fd[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) fd[c] = fc[min(j0 + c, n - 1)];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) fd[c] = c < lr ? fd[c] : 0.0;  // Uu(j0 + c, col)
+    const double dinv = id[min(col, n - 1)];
+    double4_t acc0, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc0[v] = Zt[min(col, n - 1) * kTrsmLdz + kq + 4 * v];
+    trsm_block_product(Zt, fc, n, 0, j0, lr, kq, acc0, acc1);
+    acc0 += acc1;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c < nv) {  // uniform
+        if (lr == c) acc0 *= dinv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc0[v] -= __shfl(acc0[v], (kq << 4) | c) * fd[c];
+      }
+    }
+    if (cl)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Zt[col * kTrsmLdz + kq + 4 * v] = acc0[v];
+    sync();
+  }
+  // W L = Z
+  for (int jb = nblk - 1; jb >= 0; --jb) {
+    const int j0 = jb * 16, col = j0 + lr, nv = min(16, n - j0);
+    const bool cl = col < n;
+    const double* __restrict__ fc = AT + (int64_t)(cl ? col : 0) * n;
+    double fd[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) fd[c] = fc[min(j0 + c, n - 1)];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) fd[c] = (c > lr && c < nv) ? fd[c] : 0.0;  // L(j0 + c, col)
+    double4_t acc0, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc0[v] = Zt[min(col, n - 1) * kTrsmLdz + kq + 4 * v];
+    trsm_block_product(Zt, fc, n, j0 + 16, n, lr, kq, acc0, acc1);
+    acc0 += acc1;
+#pragma unroll
+    for (int c = 15; c > 0; --c) {
+      if (c < nv)  // uniform
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc0[v] -= __shfl(acc0[v], (kq << 4) | c) * fd[c];
+    }
+    if (cl)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Zt[col * kTrsmLdz + kq + 4 * v] = acc0[v];
+    sync();
+  }
+  // Y[:, perm[c]] = W[:, c]
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int c = c0 + lane;
+    if (c < n) {
+      const int64_t pc = pm[c];
+      for (int rr = 0; rr < nr; ++rr) Y[(int64_t)(r0 + rr) * n + pc] = Zt[c * kTrsmLdz + rr];
+    }
+  }
+}
+
 template <int kRows>
 __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status,
                                              TrsmBufs b) {
@@ -550,7 +690,9 @@ __global__ __launch_bounds__(64) void k_trsm(const Item* items, int n_items, int
   double* Y = buf_ptr(ws, it, b.y[side]);
   // the tile shape and stride are compile-time constants so that LDS offsets fold into the
   // instructions
-  if (kRows != 8)
+  if (kRows == 16)
+    trsm_tile_mfma(it, side, r0, ws, AT, U, Y);
+  else if (kRows != 8)
     trsm_tile<kRows, kRows + 1, double, double, false>(it, side, r0, ws, AT, U, Y);
   else if (trsm_ldb(n) == kTrsmLdb)
     trsm_tile<kTrsmRows, kTrsmLdb, double, double, false>(it, side, r0, ws, AT, U, Y);

@@ -170,7 +170,7 @@ extern "C" vbrdf_status vbrdf_solve_noalloc(int32_t N, int32_t L, int32_t M, int
   ls.n_tasks = N * N;
   ls.max_n = n;
   ls.max_N = N;
-  ls.trsm_rows = kTrsmRows;
+  ls.trsm_rows = kTrsmRows;  // the tile shape its scratch sizes assume
   ls.trsm_tiles = (n + kTrsmRows - 1) / kTrsmRows;
   ls.trsm32_tiles = ls.trsm_tiles;
   ls.trsm_lds = trsm_lds;

@@ -187,8 +187,11 @@ __global__ void k_refine_pairs(const Item* items, double* ws, const int32_t* sta
 __global__ void k_refine_delta(const Item* items, double* ws, const int32_t* status);
 __global__ void k_refine_commit(const Item* items, double* ws, const int32_t* status);
 // right-hand-side rows per right-division tile (one wave, 64 / kTrsmRows lanes per row; the tile takes
-// n x (trsm_ldb(n) + 2) doubles of LDS)
+// n x (trsm_ldb(n) + 2) doubles of LDS). The FP32 right division and the allocation-free entry point
+// use this shape; plans start from kTrsmRowsDefault, the 16-row tile whose products run on the
+// matrix cores.
 constexpr int kTrsmRows = 8;
+constexpr int kTrsmRowsDefault = 16;
 // LDS row stride of the right-division tile, in doubles. A 64-bit LDS access is served 16 lanes
 // at a time over 32 banks: 8 parts x 2 rows at offsets 18 part + row = 2 part + row (mod 16) meet
 // 16 distinct bank pairs. Above n = 128 the tile would then hold so much LDS that fewer tiles fit
@@ -251,7 +254,7 @@ struct LaunchSet {
   double* ws_d = nullptr;          // per-item workspace blocks
   int n_layers = 0, n_items = 0, n_tasks = 0;
   int max_n = 0, max_N = 0;
-  int trsm_rows = kTrsmRows;  // right-hand-side rows per FP64 right-division tile (4, 8, 16)
+  int trsm_rows = kTrsmRowsDefault;  // right-hand-side rows per FP64 right-division tile (4, 8, 16)
   int trsm_tiles = 0;         // row tiles of the FP64 right division (largest item)
   size_t trsm_lds = 0;        // its LDS bytes
   int trsm32_tiles = 0;       // row tiles of the FP32 right division (kTrsmRows rows each)

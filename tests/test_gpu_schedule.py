@@ -1,7 +1,8 @@
 """Scheduling and tile choices on an uneven batch, through the C-ABI: the eigensolver schedules (plan
 order, longest first, persistent queue) give the same F_r bit for bit (every problem runs the same
-arithmetic); the right-division tile shapes (4, 8 or 16 rows) split each dot product over a
-different number of lanes, so they agree to rounding; the autotuner keeps a valid choice."""
+arithmetic); the right-division tile shapes (4 and 8 rows split each dot product over a different number
+of lanes, 16 rows solves by blocks on the matrix cores) sum in different orders, so they agree to
+rounding and each meets the oracle gate; the autotuner keeps a valid choice."""
 
 import numpy as np
 import pytest
@@ -40,6 +41,7 @@ def test_every_schedule_and_tile_gives_the_same_result(graph):
     s = BRDFSolver(N, L, M, P, flags=binding.FLAG_GRAPH if graph else 0)
     t, w, c = s.upload([l[4] for l in layers], [l[5] for l in layers], [l[6] for l in layers])
     stream = torch.cuda.Stream()
+    Fo = [dom.brdf(l[6], l[4], l[5], l[0], l[2], l[3]) for l in layers]
     ref = None
     for rows in (4, 8, 16):
         ref_rows = None
@@ -52,14 +54,15 @@ def test_every_schedule_and_tile_gives_the_same_result(graph):
                 s.solve_device(t, w, c, stream=stream)
             stream.synchronize()
             assert (s.status.cpu().numpy() == 0).all()
+            if ref_rows is None:
+                for i, l in enumerate(layers):
+                    assert np.abs(s.layer(i).cpu().numpy() - Fo[i]).max() < 1e-10 * np.abs(Fo[i][..., 0, 0]).max()
             if ref is None:
                 ref = s.F.clone()
-                for i, l in enumerate(layers):
-                    Fo = dom.brdf(l[6], l[4], l[5], l[0], l[2], l[3])
-                    assert np.abs(s.layer(i).cpu().numpy() - Fo).max() < 1e-10 * np.abs(Fo[..., 0, 0]).max()
             if ref_rows is None:
                 ref_rows = s.F.clone()
-                assert (s.F - ref).abs().max().item() < 1e-12 * ref.abs().max().item(), rows
+                # blocked and lane-split sums differ in order: a few 1e-12 of max |F| here
+                assert (s.F - ref).abs().max().item() < 1e-11 * ref.abs().max().item(), rows
             else:
                 assert torch.equal(s.F, ref_rows), (sched, rows)
 
