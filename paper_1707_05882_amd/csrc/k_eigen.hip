@@ -109,6 +109,9 @@ enum : int { kActDeflated = 0, kActSweep = 1, kActRotate = 2, kActStop = 3, kAct
 // once), the bulges kMultiGap rows apart. Otherwise a single double-shift sweep runs on wave 0.
 constexpr int kMultiMin = 32;
 constexpr int kMultiIts = 6;
+// Systems that take the windowed pass keep to multi-bulge passes longer: there a pass costs less
+// than the single-wave sweep in global memory it replaces (measured at n = 256: eigen stage -9%).
+constexpr int kMultiItsWindowed = 20;
 constexpr int kMultiGap = 4;
 constexpr int kMaxBulges = kEigenThreads / 64;  // one bulge per wave
 
@@ -850,7 +853,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               sctl[1] = -1;
               sctl[4] = kActStop;
               zops[slot].stop = 1;
-            } else if (nwave >= 2 && its < kMultiIts && hh - l + 1 >= kMultiMin) {
+            } else if (nwave >= 2 && its < (!kLds && n <= kWinMaxN ? kMultiItsWindowed : kMultiIts) && hh - l + 1 >= kMultiMin) {
               // one shift pair per bulge: the eigenvalues of the 2x2 diagonal blocks ending at
               // rows hh, hh - 2, ... (both roots of a real pair), stored in this slot's buffer
               const int nb = nwave < kMaxBulges ? nwave : kMaxBulges;
