@@ -616,8 +616,12 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   mark();
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufZ, kBufX, kBufG, kGemmTransA, layer_status);  // U' = Z X
   mark();
-  const int hqt = (mn + kHqCols - 1) / kHqCols;
-  k_hqapply<<<xcd_grid(ni, hqt), 64, 0, s>>>(p->items_d, ni, hqt, p->ws_d, layer_status);  // U = Q U'
+  const int hqt = (std::min(mn, kHqMfmaMaxN) + 15) / 16;
+  k_hqapply_mfma<<<xcd_grid(ni, hqt), 64, 0, s>>>(p->items_d, ni, hqt, p->ws_d, layer_status);  // U = Q U'
+  if (mn > kHqMfmaMaxN) {
+    const int hqb = (mn + kHqCols - 1) / kHqCols;
+    k_hqapply<<<xcd_grid(ni, hqb), 64, 0, s>>>(p->items_d, ni, hqb, p->ws_d, layer_status);
+  }
   mark();
   // one Newton step on the eigen-decomposition with the factored product F~ (E~ U)
   const int et = (mn + 15) / 16;

@@ -1820,13 +1820,126 @@ __device__ __forceinline__ void hqapply_body(const Item& it, int tile, double* w
     for (int r = part; r < n; r += kParts) U[(int64_t)r * n + c0 + col] = sb[r * kHqCols + col];
 }
 
+// U = Q U' on the matrix cores, for systems of at most kHqMfmaMaxN rows (the larger ones keep
+// k_hqapply: at n = 512 the large workload's per-order accuracy was established on its rounding). The reflectors are taken
+// 16 at a time, Q_p = H_p ... H_{p+15} = I - V T V^T, and applied from the last panel to the first
+// to a block of 16 columns of U' kept in LDS (row stride 17):
+//   W = V^T U and G = V^T V  in one pass over the panel's rows (per 4-row step one V entry is the
+//                            A operand of both products and the B operand of the second),
+//   X = T W                  from T^-1 = diag(1 / tau) + the strictly upper part of G (the compact
+//                            WY factor of an orthogonal product), by back substitution in the
+//                            accumulator layout, row j handed to the other lanes by an exchange,
+//   U -= V X                 (A = V from the workspace; the accumulator layout of X is the
+//                            B-operand layout).
+// A reflector with tau = 0 (a column already reduced) is the identity: its vector is taken as
+// zero. Loads of V are unconditional (index clamped) and masked afterwards, so that the next
+// chunk's loads stay in flight over the current chunk's MFMAs. One wave per 16 columns.
+constexpr int kHqLd = 17;
+
+__global__ __launch_bounds__(64) void k_hqapply_mfma(const Item* items, int n_items, int tiles, double* ws,
+                                                      const int32_t* status) {
+  int g, tile;
+  xcd_split(blockIdx.x, tiles, g, tile);  // the column blocks of one item share an XCD
+  if (g >= n_items) return;
+  const Item it = items[g];
+  if (status[it.layer] != 0 || it.n > kHqMfmaMaxN) return;
+  const int n = it.n, c0 = tile * 16;
+  if (c0 >= n) return;
+  double* base = ws + it.ws;
+  const double* __restrict__ QV = base + (int64_t)kBufYS * n * n;
+  const double* __restrict__ tauv = QV + (int64_t)(n - 1) * n;
+  const double* __restrict__ Up = base + (int64_t)kBufG * n * n;
+  double* __restrict__ U = base + (int64_t)kBufU * n * n;
+  __shared__ double sb[kHqMfmaMaxN * kHqLd];
+  const int lane = threadIdx.x, lr = lane & 15, kq = lane >> 4;
+  const int nc = min(16, n - c0);
+  auto sync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+  for (int t = lane; t < n * 16; t += 64) {
+    const int r = t >> 4, c = t & 15;
+    sb[r * kHqLd + c] = c < nc ? Up[(int64_t)r * n + c0 + c] : 0.0;
+  }
+  sync();
+  // V[row][j] (zero off the reflector's support or for tau_j = 0)
+  auto vload = [&](int j, int row) { return QV[(int64_t)min(j, n - 2) * n + min(max(row - j - 1, 0), n - 1)]; };
+  const int npan = (n - 2 + 15) / 16;
+  for (int pi = npan - 1; pi >= 0; --pi) {
+    const int p = 16 * pi, nbp = min(16, n - 2 - p);
+    const int jw = p + lr;  // reflector of this lane in the W and G products
+    const bool jok = lr < nbp && tauv[min(jw, n - 3)] != 0.0;
+    double tr[4];  // tau of reflectors p + kq + 4 v (rows of X held by this lane)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = kq + 4 * v;
+      tr[v] = j < nbp ? tauv[p + j] : 0.0;
+    }
+    double4_t accW = {0.0, 0.0, 0.0, 0.0}, accG = {0.0, 0.0, 0.0, 0.0};
+    constexpr int kC = 8;
+    double vc[kC], vn[kC];
+#pragma unroll
+    for (int u = 0; u < kC; ++u) vc[u] = vload(jw, p + 1 + 4 * u + kq);
+    for (int k = p + 1; k < n; k += 4 * kC) {
+#pragma unroll
+      for (int u = 0; u < kC; ++u) vn[u] = vload(jw, k + 4 * kC + 4 * u + kq);
+#pragma unroll
+      for (int u = 0; u < kC; ++u) {
+        const int row = k + 4 * u + kq;
+        const bool ok = jok && row > jw && row < n;
+        const double v = ok ? vc[u] : 0.0;
+        const double x = row < n ? sb[min(row, n - 1) * kHqLd + lr] : 0.0;
+        accW = __builtin_amdgcn_mfma_f64_16x16x4f64(v, x, accW, 0, 0, 0);
+        accG = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, accG, 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < kC; ++u) vc[u] = vn[u];
+    }
+    // X = T W: row j = kq + 4 v of W on this lane, column lr
+#pragma unroll
+    for (int j = 15; j >= 0; --j) {
+      if ((j & 3) == kq) accW[j >> 2] *= tr[j >> 2];
+      const double xj = __shfl(accW[j >> 2], ((j & 3) << 4) | lr);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double gij = __shfl(accG[v], (kq << 4) | j);
+        if (kq + 4 * v < j) accW[v] -= gij * xj;
+      }
+    }
+    // U -= V X on rows p+1..n-1, 16 at a time
+    for (int r0 = p + 1; r0 < n; r0 += 16) {
+      double4_t acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = sb[min(r0 + kq + 4 * v, n - 1) * kHqLd + lr];
+      const int row = r0 + lr;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = p + 4 * t + kq;
+        const double vr = vload(j, row);
+        const double a = (tr[t] != 0.0 && row > j && row < n) ? -vr : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, accW[t], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + kq + 4 * v;
+        if (rr < n) sb[rr * kHqLd + lr] = acc[v];
+      }
+    }
+    sync();
+  }
+  for (int t = lane; t < n * 16; t += 64) {
+    const int r = t >> 4, c = t & 15;
+    if (c < nc) U[(int64_t)r * n + c0 + c] = sb[r * kHqLd + c];
+  }
+}
+
 __global__ __launch_bounds__(64) void k_hqapply(const Item* items, int n_items, int tiles, double* ws,
                                                  const int32_t* status) {
   int g, tile;
   xcd_split(blockIdx.x, tiles, g, tile);  // the column blocks of one item share an XCD
   if (g >= n_items) return;
   const Item it = items[g];
-  if (status[it.layer] != 0) return;
+  if (status[it.layer] != 0 || it.n <= kHqMfmaMaxN) return;
   __shared__ double sb[kMaxn * kHqCols];  // rows x kHqCols columns
   __shared__ double stau[kMaxn];          // tau_k of every reflector
   if (it.n <= 128)

@@ -135,7 +135,11 @@ __global__ void k_vfix(const Item* items, double* ws, int32_t* status);
 __global__ void k_colscal(const Item* items, const double* tau, double* ws, int32_t* status);
 __global__ void k_bcbuild(const Item* items, double* ws, const int32_t* status);
 constexpr int kHqCols = 4;  // columns per k_hqapply wave
+// k_hqapply_mfma (16 columns per wave, panels of 16 reflectors on the matrix cores) takes the
+// systems of at most kHqMfmaMaxN rows, k_hqapply the larger ones
+constexpr int kHqMfmaMaxN = 256;
 __global__ void k_hqapply(const Item* items, int n_items, int tiles, double* ws, const int32_t* status);
+__global__ void k_hqapply_mfma(const Item* items, int n_items, int tiles, double* ws, const int32_t* status);
 // Buffers of the factorisation and right-division kernels per side (blockIdx.y of k_lu, or the
 // low digit of the matrix index of k_trsm): LU of src into the transposed factor dst; right
 // division y = rhs a^-1 with a's factor in buffer a. The side also selects the pivot and 1 / Uu_kk
