@@ -432,6 +432,8 @@ __device__ void windowed_multibulge(double* __restrict__ H, int n, double* __res
 // moves that node cluster's per-order error past what its refinement absorbs (measured 4.6e-9 of
 // max |R| against about 5e-10 with the step-by-step reduction).
 constexpr int kHessNb = 16;  // panel width: at most 16 (one 32-lane group per dot product)
+constexpr int kHessChunks = kWinMaxN / 64;  // 64-column chunks of a row of the product A_0 v
+constexpr int kHessBatch = 8;               // rows whose loads are issued together in the updates
 constexpr int kHessLds = kWin * kWinLd + kWin * kWinU;  // LDS doubles available (k_eigen_big's buffer)
 
 __device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __restrict__ QV, double* sbuf,
@@ -505,11 +507,20 @@ __device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __rest
         double acc[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) acc[r] = 0.0;
-        for (int col = c + 1 + lane; col < n; col += 64) {
-          const double vv = Vs[j * n + col - p - 1];
+        // every column chunk of the row block at once (n <= kWinMaxN: at most kHessChunks chunks),
+        // columns clamped and their v masked, so that no branch separates the loads from their use
+        double hv[kHessChunks][8], vv[kHessChunks];
 #pragma unroll
-          for (int r = 0; r < 8; ++r) acc[r] += AH(p + 1 + min(rb + r, R - 1), col) * vv;
+        for (int q = 0; q < kHessChunks; ++q) {
+          const int col = c + 1 + lane + 64 * q, cc = min(col, n - 1);
+          vv[q] = col < n ? Vs[j * n + cc - p - 1] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) hv[q][r] = AH(p + 1 + min(rb + r, R - 1), cc);
         }
+#pragma unroll
+        for (int q = 0; q < kHessChunks; ++q)
+#pragma unroll
+          for (int r = 0; r < 8; ++r) acc[r] += hv[q][r] * vv[q];
         // 8 sums over 64 lanes: halve the set at each of the first three exchanges
         {
           const bool h = lane & 32;
@@ -565,26 +576,42 @@ __device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __rest
           vc[a] = (a < nbp) ? Vs[a * n + col - p - 1] : 0.0;
           acc[a] = 0.0;
         }
-        for (int t = rp; t < R; t += 4) {
-          double x = AH(p + 1 + t, col);
+        for (int t0 = rp; t0 < R; t0 += 4 * kHessBatch) {
+          double xb[kHessBatch];
 #pragma unroll
-          for (int a = 0; a < kHessNb; ++a)
-            if (a < nbp) x -= Ys[a * n + t] * vc[a];
+          for (int b = 0; b < kHessBatch; ++b) xb[b] = AH(p + 1 + min(t0 + 4 * b, R - 1), col);
 #pragma unroll
-          for (int a = 0; a < kHessNb; ++a)
-            if (a < nbp) acc[a] += Ws[a * n + t] * x;
+          for (int b = 0; b < kHessBatch; ++b) {
+            const int t = t0 + 4 * b;
+            if (t < R) {
+              double x = xb[b];
+#pragma unroll
+              for (int a = 0; a < kHessNb; ++a)
+                if (a < nbp) x -= Ys[a * n + t] * vc[a];
+#pragma unroll
+              for (int a = 0; a < kHessNb; ++a)
+                if (a < nbp) acc[a] += Ws[a * n + t] * x;
+            }
+          }
         }
 #pragma unroll
         for (int a = 0; a < kHessNb; ++a) {
           acc[a] += __shfl_xor(acc[a], 16);
           acc[a] += __shfl_xor(acc[a], 32);
         }
-        for (int t = rp; t < R; t += 4) {
-          double x = AH(p + 1 + t, col);
+        for (int t0 = rp; t0 < R; t0 += 4 * kHessBatch) {
+          double xb[kHessBatch];
 #pragma unroll
-          for (int a = 0; a < kHessNb; ++a)
-            if (a < nbp) x -= Ys[a * n + t] * vc[a] + Vs[a * n + t] * acc[a];
-          if (live) AH(p + 1 + t, col) = x;
+          for (int b = 0; b < kHessBatch; ++b) xb[b] = AH(p + 1 + min(t0 + 4 * b, R - 1), col);
+#pragma unroll
+          for (int b = 0; b < kHessBatch; ++b) {
+            const int t = t0 + 4 * b;
+            double x = xb[b];
+#pragma unroll
+            for (int a = 0; a < kHessNb; ++a)
+              if (a < nbp) x -= Ys[a * n + min(t, R - 1)] * vc[a] + Vs[a * n + min(t, R - 1)] * acc[a];
+            if (live && t < R) AH(p + 1 + t, col) = x;
+          }
         }
       }
     }
@@ -597,11 +624,18 @@ __device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __rest
         double acc[kHessNb];
 #pragma unroll
         for (int a = 0; a < kHessNb; ++a) acc[a] = 0.0;
-        for (int t = ci; t < R; t += 16) {
-          const double x = AH(r, p + 1 + t);
+        for (int t0 = ci; t0 < R; t0 += 16 * kHessBatch) {
+          double xb[kHessBatch];
 #pragma unroll
-          for (int a = 0; a < kHessNb; ++a)
-            if (a < nbp) acc[a] += x * Ws[a * n + t];
+          for (int b = 0; b < kHessBatch; ++b) xb[b] = AH(r, p + 1 + min(t0 + 16 * b, R - 1));
+#pragma unroll
+          for (int b = 0; b < kHessBatch; ++b) {
+            const int t = t0 + 16 * b;
+            if (t < R)
+#pragma unroll
+              for (int a = 0; a < kHessNb; ++a)
+                if (a < nbp) acc[a] += xb[b] * Ws[a * n + t];
+          }
         }
 #pragma unroll
         for (int a = 0; a < kHessNb; ++a)
@@ -617,12 +651,21 @@ __device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __rest
         double vc[kHessNb];
 #pragma unroll
         for (int a = 0; a < kHessNb; ++a) vc[a] = (a < nbp) ? Vs[a * n + t] : 0.0;
-        for (int r = 0; r <= p; ++r) {
-          double x = AH(r, col);
+        for (int r0 = 0; r0 <= p; r0 += kHessBatch) {
+          double xb[kHessBatch];
 #pragma unroll
-          for (int a = 0; a < kHessNb; ++a)
-            if (a < nbp) x -= Ys[a * n + r] * vc[a];
-          AH(r, col) = x;
+          for (int b = 0; b < kHessBatch; ++b) xb[b] = AH(min(r0 + b, p), col);
+#pragma unroll
+          for (int b = 0; b < kHessBatch; ++b) {
+            const int r = r0 + b;
+            if (r <= p) {
+              double x = xb[b];
+#pragma unroll
+              for (int a = 0; a < kHessNb; ++a)
+                if (a < nbp) x -= Ys[a * n + r] * vc[a];
+              AH(r, col) = x;
+            }
+          }
         }
       }
     }
