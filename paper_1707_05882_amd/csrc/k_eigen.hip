@@ -200,8 +200,11 @@ __device__ inline int hess_line(int tid, int P, int NT) {
 // inside a window, and moves the chain kWin - 4 (bulges) rows further.
 constexpr int kWin = 88;          // window rows and columns
 constexpr int kWinLd = kWin + 1;  // LDS row stride of the window
-constexpr int kWinU = 96;         // LDS row stride of U: columns padded to whole 16-column MFMA tiles
-static_assert(kWin % 4 == 0 && kWinU % 16 == 0 && kWinU >= kWin, "MFMA tiling of the window update");
+// LDS row stride of U: at least the columns of whole 16-column MFMA tiles (96), and odd so that the
+// lanes of a column update (one row each) fall in different banks (a stride of 96 doubles put
+// all 64 lanes in one bank)
+constexpr int kWinU = 97;
+static_assert(kWin % 4 == 0 && kWinU >= (kWin + 15) / 16 * 16 && kWinU % 2 == 1, "MFMA tiling of the window update");
 static_assert(kWin * kWinLd + kWin * kWinU <= kLdsMaxn * (kLdsMaxn + 1) + 3 * 64,
               "window and U fit the LDS buffer of the LDS-resident path");
 static_assert(kWin > 4 * kMaxBulges + 4, "a window holds the whole bulge chain and lets it advance");
