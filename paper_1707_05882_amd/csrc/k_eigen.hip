@@ -1615,6 +1615,187 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
     }
     __syncthreads();
     for (int t = tid; t < n * n; t += NT) XT[t] = X[(t / n) * ld + (t % n)];
+  } else if (n <= kWinMaxN) {
+    // The same scheme for T in global memory, by groups of eigenvectors whose columns of X fit the
+    // LDS buffer (a complex pair is kept in one group); each group runs over T's blocks from its
+    // last column up.
+    const double* TG = H;
+    double* trow = srefl;  // rows s and i of the current block: [2][n]
+    const int gmax = kHessLds / n - 2;
+    const int ldx = gmax + 2;
+    for (int g0 = 0; g0 < n;) {
+    int g1 = min(n, g0 + gmax);
+    if (g1 < n && lim[g1] < 0.0) ++g1;  // the second member of a pair joins its first
+    double* X = sH;  // X(i, j) at X[i * ldx + j - g0]
+    __syncthreads();  // the previous group's columns are written out
+    for (int t = tid; t < n * ldx; t += NT) X[t] = 0.0;
+    __syncthreads();
+    // own blocks (the rest of each column stays zero below them)
+    for (int j = g0 + tid; j < g1; j += NT) {
+      const double wr = lre[j], wi = lim[j];
+      if (wi < 0.0) continue;  // second member of a complex pair: written by j - 1
+      const int b0 = (blk[j] == 0) ? j - 1 : j;
+      const int bend = (blk[b0] == 2) ? b0 + 1 : b0;
+      const bool cplx = wi > 0.0;
+      const Cx lam{wr, wi};
+      Cx xb0{0.0, 0.0}, xb1{0.0, 0.0};
+      if (bend == b0) {
+        xb0 = {1.0, 0.0};
+      } else {
+        const Cx a{TG[(int64_t)b0 * n + b0], 0.0}, bb{TG[(int64_t)b0 * n + b0 + 1], 0.0};
+        const Cx c{TG[(int64_t)(b0 + 1) * n + b0], 0.0}, d{TG[(int64_t)(b0 + 1) * n + b0 + 1], 0.0};
+        const Cx v0a = bb, v1a = csub(lam, a);  // (b, lambda - a)
+        const Cx v0b = csub(lam, d), v1b = c;   // (lambda - d, c)
+        if (cabs1(v0a) + cabs1(v1a) >= cabs1(v0b) + cabs1(v1b)) {
+          xb0 = v0a;
+          xb1 = v1a;
+        } else {
+          xb0 = v0b;
+          xb1 = v1b;
+        }
+        if (cabs1(xb0) + cabs1(xb1) == 0.0) {
+          if (j == b0) xb0 = {1.0, 0.0}; else xb1 = {1.0, 0.0};
+        }
+      }
+      X[b0 * ldx + j - g0] = xb0.re;
+      if (cplx) X[b0 * ldx + j + 1 - g0] = xb0.im;
+      if (bend > b0) {
+        X[bend * ldx + j - g0] = xb1.re;
+        if (cplx) X[bend * ldx + j + 1 - g0] = xb1.im;
+      }
+    }
+    // the next block's rows are loaded into registers while the current block is solved
+    double ps[4], pi[4];
+    auto fetch_rows = [&](int sbq, int iq) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = tid + q * NT;
+        if (c < n) {
+          ps[q] = TG[(int64_t)sbq * n + c];
+          pi[q] = TG[(int64_t)iq * n + c];
+        }
+      }
+    };
+    fetch_rows((blk[g1 - 1] == 0) ? g1 - 2 : g1 - 1, g1 - 1);
+    for (int i = g1 - 1; i >= 0;) {
+      const int sb = (blk[i] == 0) ? i - 1 : i;  // block rows [sb, i]
+      __syncthreads();  // previous block's rows are no longer read
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = tid + q * NT;
+        if (c < n) {
+          trow[c] = ps[q];
+          trow[n + c] = pi[q];
+        }
+      }
+      for (int c = tid + 4 * NT; c < n; c += NT) {  // only with fewer than n / 4 threads
+        trow[c] = TG[(int64_t)sb * n + c];
+        trow[n + c] = TG[(int64_t)i * n + c];
+      }
+      if (sb > 0) fetch_rows((blk[sb - 1] == 0) ? sb - 2 : sb - 1, sb - 1);
+      __syncthreads();
+      // four lanes per eigenvector: each sums every fourth term of the row products, combined by
+      // two lane exchanges (outside any per-eigenvector branch), then lane 0 of the four solves
+      const int lpv = (NT >= 64) ? 4 : 1;  // lanes per eigenvector (1 only for tiny test blocks)
+      for (int j0 = g0; j0 < g1; j0 += NT / lpv) {
+        const int j = j0 + tid / lpv, part = tid % lpv;
+        bool act = j < g1;
+        double wr = 0.0, wi = 0.0;
+        int b0 = 0, bend = 0;
+        if (act) {
+          wr = lre[j];
+          wi = lim[j];
+          b0 = (blk[j] == 0) ? j - 1 : j;
+          bend = (blk[b0] == 2) ? b0 + 1 : b0;
+          act = !(wi < 0.0) && i < b0;  // second member of a pair, or not above the own block
+        }
+        const bool cplx = wi > 0.0;
+        const double* ts = trow;
+        const double* ti = trow + n;
+        double p0r = 0.0, p0i = 0.0, p1r = 0.0, p1i = 0.0;
+        if (act) {
+          if (cplx) {
+            for (int c = i + 1 + part; c <= bend; c += lpv) {
+              const double xr = X[c * ldx + j - g0], xi = X[c * ldx + j + 1 - g0];
+              p0r -= ts[c] * xr;
+              p0i -= ts[c] * xi;
+              p1r -= ti[c] * xr;
+              p1i -= ti[c] * xi;
+            }
+          } else {
+            for (int c = i + 1 + part; c <= bend; c += lpv) {
+              const double xc = X[c * ldx + j - g0];
+              p0r -= ts[c] * xc;
+              p1r -= ti[c] * xc;
+            }
+          }
+        }
+        if (lpv == 4) {
+          p0r += __shfl_xor(p0r, 1);
+          p0i += __shfl_xor(p0i, 1);
+          p1r += __shfl_xor(p1r, 1);
+          p1i += __shfl_xor(p1i, 1);
+          p0r += __shfl_xor(p0r, 2);
+          p0i += __shfl_xor(p0i, 2);
+          p1r += __shfl_xor(p1r, 2);
+          p1i += __shfl_xor(p1i, 2);
+        }
+        if (!act || part != 0) continue;
+        const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
+        const Cx lam{wr, wi};
+        const Cx r0{p0r, p0i}, r1{p1r, p1i};
+        if (sb == i) {
+          const Cx d0 = csub(Cx{ti[i], 0.0}, lam);
+          const Cx xi = (cabs1(d0) <= same) ? Cx{0.0, 0.0} : cdiv(r0, cguard(d0, smin));
+          X[i * ldx + j - g0] = xi.re;
+          if (cplx) X[i * ldx + j + 1 - g0] = xi.im;
+        } else if (cabs1(csub(Cx{lre[sb], lim[sb]}, lam)) <= same || cabs1(csub(Cx{lre[i], lim[i]}, lam)) <= same) {
+          X[sb * ldx + j - g0] = 0.0;
+          X[i * ldx + j - g0] = 0.0;
+          if (cplx) {
+            X[sb * ldx + j + 1 - g0] = 0.0;
+            X[i * ldx + j + 1 - g0] = 0.0;
+          }
+        } else {
+          Cx x0, x1;
+          csolve2(csub(Cx{ts[sb], 0.0}, lam), Cx{ts[i], 0.0}, Cx{ti[sb], 0.0}, csub(Cx{ti[i], 0.0}, lam), r0, r1,
+                  smin, x0, x1);
+          X[sb * ldx + j - g0] = x0.re;
+          X[i * ldx + j - g0] = x1.re;
+          if (cplx) {
+            X[sb * ldx + j + 1 - g0] = x0.im;
+            X[i * ldx + j + 1 - g0] = x1.im;
+          }
+        }
+      }
+      i = sb - 1;
+    }
+    __syncthreads();
+    // normalise (max modulus component -> 1) and write the group's columns out
+    for (int j = g0 + tid; j < g1; j += NT) {
+      const double wi = lim[j];
+      if (wi < 0.0) continue;
+      const bool cplx = wi > 0.0;
+      double mx = 0.0;
+      for (int q = 0; q < n; ++q) {
+        double v = fabs(X[q * ldx + j - g0]);
+        if (cplx) v += fabs(X[q * ldx + j + 1 - g0]);
+        mx = fmax(mx, v);
+      }
+      const double sc = (mx > 0.0) ? 1.0 / mx : 1.0;
+      for (int q = 0; q < n; ++q) {
+        X[q * ldx + j - g0] *= sc;
+        if (cplx) X[q * ldx + j + 1 - g0] *= sc;
+      }
+    }
+    __syncthreads();
+    const int gw = g1 - g0;
+    for (int t = tid; t < n * gw; t += NT) {
+      const int q = t / gw, jj = t - (t / gw) * gw;
+      XT[(int64_t)q * n + g0 + jj] = X[q * ldx + jj];
+    }
+    g0 = g1;
+    }
   } else {
 #define TV(r, c) H[(int64_t)(r) * ld + (c)]
 #define XV(r, c) XT[(int64_t)(r) * n + (c)]
