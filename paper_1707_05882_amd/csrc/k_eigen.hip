@@ -1694,9 +1694,9 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       }
       if (sb > 0) fetch_rows((blk[sb - 1] == 0) ? sb - 2 : sb - 1, sb - 1);
       __syncthreads();
-      // four lanes per eigenvector: each sums every fourth term of the row products, combined by
-      // two lane exchanges (outside any per-eigenvector branch), then lane 0 of the four solves
-      const int lpv = (NT >= 64) ? 4 : 1;  // lanes per eigenvector (1 only for tiny test blocks)
+      // eight lanes per eigenvector (a group has at most about 64 of them): each sums every eighth
+      // term of the row products, combined by three lane exchanges, then lane 0 of the eight solves
+      const int lpv = 8;
       for (int j0 = g0; j0 < g1; j0 += NT / lpv) {
         const int j = j0 + tid / lpv, part = tid % lpv;
         bool act = j < g1;
@@ -1730,15 +1730,12 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
             }
           }
         }
-        if (lpv == 4) {
-          p0r += __shfl_xor(p0r, 1);
-          p0i += __shfl_xor(p0i, 1);
-          p1r += __shfl_xor(p1r, 1);
-          p1i += __shfl_xor(p1i, 1);
-          p0r += __shfl_xor(p0r, 2);
-          p0i += __shfl_xor(p0i, 2);
-          p1r += __shfl_xor(p1r, 2);
-          p1i += __shfl_xor(p1i, 2);
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+          p0r += __shfl_xor(p0r, o);
+          p0i += __shfl_xor(p0i, o);
+          p1r += __shfl_xor(p1r, o);
+          p1i += __shfl_xor(p1i, o);
         }
         if (!act || part != 0) continue;
         const double smin = fmax(kUlp * (fabs(wr) + fabs(wi)), kSafeMin);
