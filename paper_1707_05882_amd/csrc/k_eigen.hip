@@ -443,7 +443,7 @@ __device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __rest
                                    double* sred) {
   const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = NT >> 6;
   int nb = kHessNb;
-  while (nb > 4 && 3 * nb * n + 2 * n + 64 > kHessLds) nb -= 4;
+  while (nb > 4 && 3 * nb * n + 2 * n + 64 + 8 * 16 * 17 > kHessLds) nb -= 4;
   double* Vs = sbuf;          // V[t][a] at Vs[a n + t] (row p + 1 + t)
   double* Ys = Vs + nb * n;   // Y[t][a] at Ys[a n + t]; after the panel, Y_top[r][a] at Ys[a n + r]
   double* Ws = Ys + nb * n;   // W[t][a] at Ws[a n + t]
@@ -566,109 +566,122 @@ __device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __rest
       }
     }
     __syncthreads();
-    // trailing columns p+nbp..n-1 on rows p+1..n-1: X = A_0 - Y V^T, X <- X - V (W^T X).
-    // Lane = 16 columns x 4 row parts; a wave covers 16 columns, its 4 parts combine W^T X.
+    // The panel's update of the rest of the matrix, on the matrix cores (v_mfma_f64_16x16x4), as
+    // tasks of one wave each:
+    //  * a block of 16 trailing columns (p+nbp..n-1) on rows p+1..n-1: X = A_0 - Y V^T tile by tile
+    //    while W^T X is summed over the row tiles (the accumulator layout of X is the B-operand
+    //    layout), then a second pass X = A_0 - Y V^T - V (W^T X) stores the tiles;
+    //  * a block of 16 rows above the panel (0..p) on columns p+1..n-1: Y_top = A_0 W (staged
+    //    through LDS to serve as an A operand), then A_0 - Y_top V^T.
+    // The two kinds touch disjoint parts of H and only read V, Y, W. Panel columns a >= nbp of
+    // V, Y, W are masked (they hold an earlier panel's values); rows past the end are clamped and
+    // masked. The next tile's loads are issued before the current tile's MFMAs.
     {
-      const int ci = lane & 15, rp = lane >> 4;
-      for (int cb = p + nbp + 16 * wv; cb < n; cb += 16 * nw) {
-        const int col = min(cb + ci, n - 1);
-        const bool live = cb + ci < n;
-        double vc[kHessNb], acc[kHessNb];
+      const int lr = lane & 15, kq = lane >> 4;
+      const int ct0 = p + nbp;                   // first trailing column
+      const int ncb = (n - ct0 + 15) >> 4;       // trailing column blocks
+      const int nrb = (R + 15) >> 4;             // row tiles of the trailing rows
+      const int ntb = (p + 1 + 15) >> 4;         // row blocks above the panel
+      double* Yt = zs + 48 + wv * (16 * 17);     // per wave: Y_top block [16][17]
+      for (int task = wv; task < ncb + ntb; task += nw) {
+        if (task < ncb) {
+          const int col = ct0 + task * 16 + lr, colc = min(col, n - 1);
+          double bv[4];  // B of Y V^T: V[col][a], a = 4 t + kq
 #pragma unroll
-        for (int a = 0; a < kHessNb; ++a) {
-          vc[a] = (a < nbp) ? Vs[a * n + col - p - 1] : 0.0;
-          acc[a] = 0.0;
-        }
-        for (int t0 = rp; t0 < R; t0 += 4 * kHessBatch) {
-          double xb[kHessBatch];
+          for (int t = 0; t < 4; ++t) {
+            const int a = 4 * t + kq;
+            bv[t] = a < nbp ? Vs[a * n + colc - p - 1] : 0.0;
+          }
+          auto load_tile = [&](int rb, double4_t& x) {
 #pragma unroll
-          for (int b = 0; b < kHessBatch; ++b) xb[b] = AH(p + 1 + min(t0 + 4 * b, R - 1), col);
+            for (int v = 0; v < 4; ++v) x[v] = AH(p + 1 + min(16 * rb + kq + 4 * v, R - 1), colc);
+          };
+          auto minus_yv = [&](int rb, double4_t& x) {
+            const int tr = 16 * rb + lr;  // A-operand row of this lane
 #pragma unroll
-          for (int b = 0; b < kHessBatch; ++b) {
-            const int t = t0 + 4 * b;
-            if (t < R) {
-              double x = xb[b];
-#pragma unroll
-              for (int a = 0; a < kHessNb; ++a)
-                if (a < nbp) x -= Ys[a * n + t] * vc[a];
-#pragma unroll
-              for (int a = 0; a < kHessNb; ++a)
-                if (a < nbp) acc[a] += Ws[a * n + t] * x;
+            for (int t = 0; t < 4; ++t) {
+              const int a = 4 * t + kq;
+              const double y = Ys[a * n + min(tr, R - 1)];
+              x = __builtin_amdgcn_mfma_f64_16x16x4f64((a < nbp && tr < R) ? -y : 0.0, bv[t], x, 0, 0, 0);
             }
-          }
-        }
+          };
+          double4_t wt = {0.0, 0.0, 0.0, 0.0};  // W^T X: rows a = kq + 4 v, column lr
+          double4_t xc, xn;
+          load_tile(0, xc);
+          for (int rb = 0; rb < nrb; ++rb) {
+            load_tile(min(rb + 1, nrb - 1), xn);
+            minus_yv(rb, xc);
 #pragma unroll
-        for (int a = 0; a < kHessNb; ++a) {
-          acc[a] += __shfl_xor(acc[a], 16);
-          acc[a] += __shfl_xor(acc[a], 32);
-        }
-        for (int t0 = rp; t0 < R; t0 += 4 * kHessBatch) {
-          double xb[kHessBatch];
-#pragma unroll
-          for (int b = 0; b < kHessBatch; ++b) xb[b] = AH(p + 1 + min(t0 + 4 * b, R - 1), col);
-#pragma unroll
-          for (int b = 0; b < kHessBatch; ++b) {
-            const int t = t0 + 4 * b;
-            double x = xb[b];
-#pragma unroll
-            for (int a = 0; a < kHessNb; ++a)
-              if (a < nbp) x -= Ys[a * n + min(t, R - 1)] * vc[a] + Vs[a * n + min(t, R - 1)] * acc[a];
-            if (live && t < R) AH(p + 1 + t, col) = x;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // rows 0..p, columns p+1..n-1: Y_top = A_0 W (lane = 16 columns x 4 rows), then A_0 - Y_top V^T
-    {
-      const int ci = lane & 15, rq = lane >> 4;
-      for (int rb = 4 * wv; rb <= p; rb += 4 * nw) {
-        const int r = min(rb + rq, p);
-        double acc[kHessNb];
-#pragma unroll
-        for (int a = 0; a < kHessNb; ++a) acc[a] = 0.0;
-        for (int t0 = ci; t0 < R; t0 += 16 * kHessBatch) {
-          double xb[kHessBatch];
-#pragma unroll
-          for (int b = 0; b < kHessBatch; ++b) xb[b] = AH(r, p + 1 + min(t0 + 16 * b, R - 1));
-#pragma unroll
-          for (int b = 0; b < kHessBatch; ++b) {
-            const int t = t0 + 16 * b;
-            if (t < R)
-#pragma unroll
-              for (int a = 0; a < kHessNb; ++a)
-                if (a < nbp) acc[a] += xb[b] * Ws[a * n + t];
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < kHessNb; ++a)
-          for (int o = 8; o > 0; o >>= 1) acc[a] += __shfl_xor(acc[a], o);
-        if (ci == 0 && rb + rq <= p)
-#pragma unroll
-          for (int a = 0; a < kHessNb; ++a)
-            if (a < nbp) Ys[a * n + r] = acc[a];
-      }
-      __syncthreads();
-      for (int t = tid; t < R; t += NT) {  // lanes along columns, each thread all rows 0..p
-        const int col = p + 1 + t;
-        double vc[kHessNb];
-#pragma unroll
-        for (int a = 0; a < kHessNb; ++a) vc[a] = (a < nbp) ? Vs[a * n + t] : 0.0;
-        for (int r0 = 0; r0 <= p; r0 += kHessBatch) {
-          double xb[kHessBatch];
-#pragma unroll
-          for (int b = 0; b < kHessBatch; ++b) xb[b] = AH(min(r0 + b, p), col);
-#pragma unroll
-          for (int b = 0; b < kHessBatch; ++b) {
-            const int r = r0 + b;
-            if (r <= p) {
-              double x = xb[b];
-#pragma unroll
-              for (int a = 0; a < kHessNb; ++a)
-                if (a < nbp) x -= Ys[a * n + r] * vc[a];
-              AH(r, col) = x;
+            for (int t = 0; t < 4; ++t) {
+              const int tk = 16 * rb + 4 * t + kq;  // row of X in this k-step
+              const double w = Ws[lr * n + min(tk, R - 1)];
+              wt = __builtin_amdgcn_mfma_f64_16x16x4f64((lr < nbp && tk < R) ? w : 0.0, xc[t], wt, 0, 0, 0);
             }
+            xc = xn;
           }
+          load_tile(0, xc);
+          for (int rb = 0; rb < nrb; ++rb) {
+            load_tile(min(rb + 1, nrb - 1), xn);
+            minus_yv(rb, xc);
+            const int tr = 16 * rb + lr;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int a = 4 * t + kq;
+              const double v = Vs[a * n + min(tr, R - 1)];
+              xc = __builtin_amdgcn_mfma_f64_16x16x4f64((a < nbp && tr < R) ? -v : 0.0, wt[t], xc, 0, 0, 0);
+            }
+            if (col < n)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int t = 16 * rb + kq + 4 * v;
+                if (t < R) AH(p + 1 + t, col) = xc[v];
+              }
+            xc = xn;
+          }
+        } else {
+          const int r0 = (task - ncb) * 16;     // rows r0..r0+15 (those <= p)
+          const int ra = min(r0 + lr, p);       // A-operand row of this lane
+          // Y_top = A_0[rows, p+1..n-1] W: A = A_0 (row lr, column 4 t + kq), B = W[column][a]
+          double4_t yt = {0.0, 0.0, 0.0, 0.0};
+          constexpr int kC = 8;
+          double ac[kC], an[kC];
+#pragma unroll
+          for (int u = 0; u < kC; ++u) ac[u] = AH(ra, p + 1 + min(4 * u + kq, R - 1));
+          for (int k = 0; k < R; k += 4 * kC) {
+#pragma unroll
+            for (int u = 0; u < kC; ++u) an[u] = AH(ra, p + 1 + min(k + 4 * kC + 4 * u + kq, R - 1));
+#pragma unroll
+            for (int u = 0; u < kC; ++u) {
+              const int tk = k + 4 * u + kq;
+              const double w = Ws[lr * n + min(tk, R - 1)];
+              yt = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u], (lr < nbp && tk < R) ? w : 0.0, yt, 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kC; ++u) ac[u] = an[u];
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Yt[(kq + 4 * v) * 17 + lr] = yt[v];
+          wave_sync();
+          double ya[4];  // A of Y_top V^T: Y_top[row lr][a = 4 t + kq]
+#pragma unroll
+          for (int t = 0; t < 4; ++t) ya[t] = -Yt[lr * 17 + 4 * t + kq];
+          for (int cb = 0; cb * 16 < R; ++cb) {
+            const int col = p + 1 + cb * 16 + lr, colc = min(col, n - 1);
+            double4_t x;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) x[v] = AH(min(r0 + kq + 4 * v, p), colc);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int a = 4 * t + kq;
+              const double b = a < nbp ? Vs[a * n + colc - p - 1] : 0.0;
+              x = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[t], b, x, 0, 0, 0);
+            }
+            if (col < n)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                if (r0 + kq + 4 * v <= p) AH(r0 + kq + 4 * v, col) = x[v];
+          }
+          wave_sync();  // Yt is read before the wave's next task rewrites it
         }
       }
     }
