@@ -61,7 +61,7 @@ def stage_work(stage, layers):
 KERNEL_SOURCE = {"k_eigen": "k_eigen.hip", "k_eigen_big": "k_eigen.hip", "k_hqapply": "k_eigen.hip", "k_hqapply_mfma": "k_eigen.hip", "k_lu": "k_bc.hip", "k_trsm": "k_bc.hip", "k_vfix": "k_bc.hip",
                  "k_bcbuild": "k_bc.hip", "k_colscal": "k_bc.hip", "k_response": "k_bc.hip", "k_gemm": "k_gemm.hip",
                  "k_assemble": "k_assemble.hip", "k_legendre": "k_assemble.hip", "k_validate": "k_assemble.hip",
-                 "k_synth": "k_synth.hip", "k_refine": "k_refine.hip"}
+                 "k_synth": "k_synth.hip", "k_synth_mfma": "k_synth.hip", "k_refine": "k_refine.hip"}
 
 
 def stage_kernels(stage):

@@ -687,7 +687,7 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   mark();
   if (p->stacked) enqueue_stacks(*p, base, layer_status, s);
   mark();
-  k_synth<<<p->n_tasks, 256, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
+  k_synth_mfma<<<p->n_tasks, 64, 0, s>>>(p->tasks_d, p->layers_d, p->items_d, p->quad_d, p->ws_d, F_r, layer_status);
   if (beams) enqueue_beam_synth(*p, F_beam, layer_status, s);
   if (p->save) k_copy_status<<<(p->n_layers + 255) / 256, 256, 0, s>>>(layer_status, p->status_d, p->n_layers);
   mark();

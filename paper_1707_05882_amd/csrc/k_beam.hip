@@ -113,7 +113,7 @@ __global__ void k_beam_resp(const Item* items, const double* tau, const double* 
 }
 
 // F_beam[i][j][k][r][p] = 1/(2 mu0_j) sum_m c_m tau_rp(m dphi_k) R_beam^m[(i, r), 4 j + p]: the
-// synthesis of eq. 12 and 39 with the horizontal irradiance mu0_j I0 (as k_synth for the nodes).
+// synthesis of eq. 12 and 39 with the horizontal irradiance mu0_j I0 (as k_synth_mfma for the nodes).
 // Outgoing index i < N: the Gauss nodes (kBufB4); N <= i < N + n_out: the extra outgoing
 // directions (kBufB5, rows 4 (i - N) + r).
 __global__ __launch_bounds__(256) void k_beam_synth(const BeamTask* tasks, const Layer* layers, const Item* items,

@@ -4,53 +4,109 @@
 // dphi_k = 2 pi k / n_dphi. tau_rp is cos on the IQ-IQ and UV-UV blocks, +sin on the UV<-IQ block
 // and -sin on the IQ<-UV block (the diagonal of Phi_1^m for an IQ input, of Phi_2^m for a UV input).
 // The 1/(2 mu_q) combines the 1/2 of the Stokes series with the horizontal irradiance mu_q I0 of the
-// BRDF definition. One workgroup per (layer, i, q): the 16 M response values are staged in LDS and
-// the n_dphi x 16 outputs are written contiguously. Angles are taken from a table indexed by
-// (m k) mod n_dphi, so no phase is accumulated in floating point.
+// BRDF definition. Angles are taken from a table indexed by (m k) mod n_dphi, so no phase is
+// accumulated in floating point.
 #include "vbrdf_internal.hpp"
 
 namespace vbrdf {
 
-__global__ __launch_bounds__(256) void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items,
-                                                const double* quad, const double* ws, double* F,
-                                                const int32_t* status) {
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// The synthesis as a product on the matrix cores: for a fixed row block i and two input
+// nodes q0, q0 + 1, out[k][e] = sum_m T[k][m] R^m[e] over the 16 entries e of one kind (the 8 cos
+// entries of each node, or the 8 sin entries), with T[k][m] = c_m cos(2 pi m k / n_dphi) or
+// c_m sin(...): one v_mfma_f64_16x16x4 per 16 azimuths, 4 orders and kind. A operand = T from LDS
+// tables (row = azimuth lane % 16, k = order lane / 16 + 4 t), B operand = R^m[e] gathered from the
+// items' workspaces (k = order, column = entry lane % 16), loaded one step ahead and shared by up to
+// 8 azimuth tiles; the sign of the IQ <- UV block and 1 / (2 mu_q) come in when storing. One wave
+// per task with even q (odd-q tasks are covered by their even neighbour and return at once).
+constexpr int kSynthTiles = 8;  // azimuth tiles of 16 held in registers per pass over the orders
+
+__global__ __launch_bounds__(64) void k_synth_mfma(const SynthTask* tasks, const Layer* layers, const Item* items,
+                                                    const double* quad, const double* ws, double* F,
+                                                    const int32_t* status) {
   const SynthTask tk = tasks[blockIdx.x];
+  if (tk.q & 1) return;
   const Layer ly = layers[tk.layer];
   const int N = ly.N, M = ly.M, nphi = ly.n_dphi, n = 4 * N;
-  double* out = F + ly.out_off + ((int64_t)tk.i * N + tk.q) * nphi * 16;
-  const int tid = threadIdx.x, NT = blockDim.x;
+  const int lane = threadIdx.x, lr = lane & 15, kq = lane >> 4;
+  const int nq = min(2, N - tk.q);  // input nodes of this task
   if (status[tk.layer] != 0) {
     const double nanv = __builtin_nan("");
-    for (int t = tid; t < nphi * 16; t += NT) out[t] = nanv;
+    double* out = F + ly.out_off + ((int64_t)tk.i * N + tk.q) * nphi * 16;
+    for (int t = lane; t < nq * nphi * 16; t += 64) out[t] = nanv;
     return;
   }
-  __shared__ double sR[kSynthMaxM][16];
   __shared__ double sc[kSynthMaxPhi], ss[kSynthMaxPhi];
-  for (int t = tid; t < M * 16; t += NT) {
-    const int m = t / 16, rp = t % 16, r = rp / 4, p = rp % 4;
-    const Item it = items[ly.item0 + m];
-    sR[m][rp] = ws[it.ws + (int64_t)kBufE * n * n + (int64_t)(4 * tk.i + r) * n + 4 * tk.q + p];
-  }
-  for (int t = tid; t < nphi; t += NT) {
+  __shared__ int64_t sws[kSynthMaxM];
+  for (int t = lane; t < nphi; t += 64) {
     const double a = 6.283185307179586 * (double)t / (double)nphi;
     sc[t] = cos(a);
     ss[t] = sin(a);
   }
-  __syncthreads();
-  const double inv2mu = 0.5 / quad[ly.quad_off + tk.q];
-  for (int t = tid; t < nphi * 16; t += NT) {
-    const int k = t / 16, rp = t % 16, r = rp / 4, p = rp % 4;
-    const bool riq = r < 2, piq = p < 2;
-    const int kind = (riq == piq) ? 0 : (piq ? 1 : 2);  // cos, +sin, -sin
-    double acc = (kind == 0) ? sR[0][rp] : 0.0;
-    int ph = 0;  // (m k) mod nphi
-    for (int m = 1; m < M; ++m) {
-      ph += k;
-      if (ph >= nphi) ph -= nphi;
-      const double f = (kind == 0) ? sc[ph] : (kind == 1 ? ss[ph] : -ss[ph]);
-      acc += 2.0 * f * sR[m][rp];
+  for (int t = lane; t < M; t += 64) sws[t] = items[ly.item0 + t].ws + (int64_t)kBufE * n * n;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // entry of this lane's column: node q = q0 + lr / 8, (r, p) of the cos list or of the sin list
+  const int e8 = lr & 7, qq = min(tk.q + (lr >> 3), N - 1);
+  const int rc = (e8 < 4) ? (e8 >> 1) : 2 + ((e8 - 4) >> 1), pc = (e8 < 4) ? (e8 & 1) : 2 + (e8 & 1);
+  const int rs = (e8 < 4) ? 2 + (e8 >> 1) : (e8 - 4) >> 1, ps = (e8 < 4) ? (e8 & 1) : 2 + (e8 & 1);
+  const int64_t oc = (int64_t)(4 * tk.i + rc) * n + 4 * qq + pc;
+  const int64_t os = (int64_t)(4 * tk.i + rs) * n + 4 * qq + ps;
+  const int nsteps = (M + 3) >> 2;
+  for (int kg = 0; kg * 16 * kSynthTiles < nphi; ++kg) {
+    const int kt0 = kg * kSynthTiles, ntile = min(kSynthTiles, (nphi + 15) / 16 - kt0);
+    double4_t acc_c[kSynthTiles], acc_s[kSynthTiles];
+#pragma unroll
+    for (int t = 0; t < kSynthTiles; ++t) {
+      acc_c[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      acc_s[t] = (double4_t){0.0, 0.0, 0.0, 0.0};
     }
-    out[t] = acc * inv2mu;
+    auto gather = [&](int st, double& bcv, double& bsv) {
+      const int m = min(4 * st + kq, M - 1);
+      const double* R = ws + sws[m];
+      bcv = R[oc];
+      bsv = R[os];
+    };
+    double bc, bs, bcn, bsn;
+    gather(0, bc, bs);
+    for (int st = 0; st < nsteps; ++st) {
+      gather(min(st + 1, nsteps - 1), bcn, bsn);
+      const int m = 4 * st + kq;
+      const bool mok = m < M;
+      const double cm = (m == 0) ? 1.0 : 2.0;
+#pragma unroll
+      for (int t = 0; t < kSynthTiles; ++t) {
+        if (t < ntile) {  // uniform
+          const int k = min((kt0 + t) * 16 + lr, nphi - 1);
+          const int ph = (int)(((int64_t)m * k) % nphi);
+          const double ac = mok ? cm * sc[ph] : 0.0;
+          const double as = (mok && m > 0) ? cm * ss[ph] : 0.0;
+          acc_c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac, mok ? bc : 0.0, acc_c[t], 0, 0, 0);
+          acc_s[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, mok ? bs : 0.0, acc_s[t], 0, 0, 0);
+        }
+      }
+      bc = bcn;
+      bs = bsn;
+    }
+    // store: accumulator row = azimuth kq + 4 v of the tile, column = entry lr
+    if (tk.q + (lr >> 3) < N) {
+      const double inv2mu = 0.5 / quad[ly.quad_off + qq];
+      const double sgn = (rs < 2) ? -1.0 : 1.0;  // IQ <- UV: -sin; UV <- IQ: +sin
+      double* outq = F + ly.out_off + ((int64_t)tk.i * N + qq) * nphi * 16;
+#pragma unroll
+      for (int t = 0; t < kSynthTiles; ++t) {
+        if (t < ntile)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int k = (kt0 + t) * 16 + kq + 4 * v;
+            if (k < nphi) {
+              outq[(int64_t)k * 16 + rc * 4 + pc] = acc_c[t][v] * inv2mu;
+              outq[(int64_t)k * 16 + rs * 4 + ps] = sgn * acc_s[t][v] * inv2mu;
+            }
+          }
+      }
+    }
   }
 }
 

@@ -246,7 +246,7 @@ __global__ void k_stack_x(const Item* items, const StackTask* tasks, const Layer
                           int base_kind, const double* base, double* ws, int32_t* status);
 __global__ void k_stack_finish(const Item* items, const Layer* layers, const double* quad, double* ws,
                                const int32_t* status);
-__global__ void k_synth(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
+__global__ void k_synth_mfma(const SynthTask* tasks, const Layer* layers, const Item* items, const double* quad,
                         const double* ws, double* F, const int32_t* status);
 // Device tables and launch shape of a solve: the plan's, or those of the allocation-free entry
 // point (tables inside its static scratch array).
