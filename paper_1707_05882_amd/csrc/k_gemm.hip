@@ -6,7 +6,8 @@
 // refinement. Each item carries its own n; the grid covers the largest n and surplus tiles exit.
 //
 // Tiling: 64 x 64 output tile per workgroup of 4 waves; each wave owns a 32 x 32 quadrant as 2 x 2
-// v_mfma_f64_16x16x4 tiles; K is staged through LDS 16 at a time. Lane layout of the 16x16x4 FP64
+// v_mfma_f64_16x16x4 tiles; K is staged through LDS 16 at a time, the next step's tiles loaded into
+// registers while the current step is multiplied. Lane layout of the 16x16x4 FP64
 // MFMA (measured on gfx950 with an in-bounds probe): A element (row = lane % 16, k = lane / 16),
 // B element (k = lane / 16, col = lane % 16), accumulator register v (row = lane / 16 + 4 v,
 // col = lane % 16).
@@ -45,39 +46,41 @@ __global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
+  // The next K step's tiles go to registers while the current step is multiplied; loads are
+  // unconditional (indices clamped, values outside the matrix masked after the load).
+  constexpr int kPer = kGT * kGK / 256;
+  double ra[kPer], rb[kPer];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      const int ar = transA ? t % kGT : t / kGK, ak = transA ? t / kGT : t % kGK;
+      const int gr = min(r0 + ar, n - 1), gk = min(k0 + ak, n - 1);
+      const double v = transA ? A[(int64_t)gk * n + gr] : A[(int64_t)gr * n + gk];
+      ra[q] = (r0 + ar < n && k0 + ak < n) ? v : 0.0;
+      const int bc = transB ? t / kGK : t % kGT, bk = transB ? t % kGK : t / kGT;
+      const int hc = min(c0 + bc, n - 1), hk = min(k0 + bk, n - 1);
+      const double w = transB ? B[(int64_t)hc * n + hk] : B[(int64_t)hk * n + hc];
+      rb[q] = (k0 + bk < n && c0 + bc < n) ? w : 0.0;
+    }
+  };
+  load(0);
   for (int k0 = 0; k0 < n; k0 += kGK) {
     __syncthreads();
-    // A tile: 64 rows x 16 k
-    for (int t = tid; t < kGT * kGK; t += 256) {
-      int r, k;
-      double v;
-      if (transA) {  // element (row, k) of op(A) lives at A[k * n + row]: rows fastest
-        r = t % kGT;
-        k = t / kGT;
-        v = (r0 + r < n && k0 + k < n) ? A[(int64_t)(k0 + k) * n + r0 + r] : 0.0;
-      } else {
-        k = t % kGK;
-        r = t / kGK;
-        v = (r0 + r < n && k0 + k < n) ? A[(int64_t)(r0 + r) * n + k0 + k] : 0.0;
-      }
-      sA[r][k] = v;
-    }
-    // B tile: 16 k x 64 cols
-    for (int t = tid; t < kGK * kGT; t += 256) {
-      int c, k;
-      double v;
-      if (transB) {  // element (k, col) of op(B) lives at B[col * n + k]: k fastest
-        k = t % kGK;
-        c = t / kGK;
-        v = (k0 + k < n && c0 + c < n) ? B[(int64_t)(c0 + c) * n + k0 + k] : 0.0;
-      } else {
-        c = t % kGT;
-        k = t / kGT;
-        v = (k0 + k < n && c0 + c < n) ? B[(int64_t)(k0 + k) * n + c0 + c] : 0.0;
-      }
-      sB[k][c] = v;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      if (transA)
+        sA[t % kGT][t / kGT] = ra[q];
+      else
+        sA[t / kGK][t % kGK] = ra[q];
+      if (transB)
+        sB[t % kGK][t / kGK] = rb[q];
+      else
+        sB[t / kGT][t % kGT] = rb[q];
     }
     __syncthreads();
+    if (k0 + kGK < n) load(k0 + kGK);
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 4) {
       double a[2], b[2];
