@@ -208,6 +208,8 @@ __host__ __device__ inline int trsm_ldb_rows(int n, int rows) { return rows == 8
 // Right-division tile geometry for `rows` rows per tile over systems up to max_n.
 inline int trsm_tiles_for(int max_n, int rows) { return (max_n + rows - 1) / rows; }
 inline size_t trsm_lds_for(int max_n, int rows) {
+  // the 16-row tile keeps only itself in LDS (stride 17; the factor is read from the workspace)
+  if (rows == 16) return sizeof(double) * (size_t)max_n * 17;
   return sizeof(double) * (size_t)max_n * (trsm_ldb_rows(max_n, rows) + 2);
 }
 
