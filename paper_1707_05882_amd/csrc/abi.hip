@@ -629,7 +629,7 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufE, kBufU, kBufG, 0, layer_status);  // E~ U
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufG, kBufZ, kGemmTransC, layer_status);  // (F~ E~ U)^T
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, layer_status);  // U^T
-  k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, LuBufs{{kBufX, kBufX}, {kBufYS, kBufYS}});
+  launch_lu(dim3(ni, 1), s, p->items_d, p->ws_d, layer_status, p->max_n, LuBufs{{kBufX, kBufX}, {kBufYS, kBufYS}});
   launch_trsm(p->trsm_rows, dim3(xcd_grid(ni, p->trsm_tiles)), p->trsm_lds, s, p->items_d, ni, p->trsm_tiles,
               p->ws_d, layer_status, TrsmBufs{{kBufYS, kBufYS}, {kBufZ, kBufZ}, {kBufG, kBufG}, 1, 0});  // Y^T = (G U)^T U^-T
   k_refine_lam<<<dim3((mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, layer_status);
@@ -670,11 +670,11 @@ void enqueue_solve(const LaunchSet& ls, const double* tau, const double* omega, 
     lf.only_flagged = 1;
     TrsmBufs tf = trb;
     tf.only_flagged = 1;
-    k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, lf);
+    launch_lu(dim3(ni, 2), s, p->items_d, p->ws_d, layer_status, p->max_n, lf);
     launch_trsm(p->trsm_rows, xg, p->trsm_lds, s, p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, tf);
     mark();
   } else {
-    k_lu<<<dim3(ni, 2), 1024, 0, s>>>(p->items_d, p->ws_d, layer_status, lub);
+    launch_lu(dim3(ni, 2), s, p->items_d, p->ws_d, layer_status, p->max_n, lub);
     mark();
     launch_trsm(p->trsm_rows, xg, p->trsm_lds, s, p->items_d, ni, p->trsm_tiles, p->ws_d, layer_status, trb);
     mark();
@@ -713,7 +713,7 @@ static void enqueue_stacks(const LaunchSet& ls, const double* base, int32_t* lay
     const dim3 gg(gt, gt, cnt);
     k_gemm<<<gg, 256, 0, s>>>(it, p->ws_d, kBufG, kBufE, kBufZ, kGemmNegate | kGemmAccumulate, layer_status);  // I - X R
     k_gemm<<<gg, 256, 0, s>>>(it, p->ws_d, kBufG, kBufF, kBufYS, 0, layer_status);                             // X T
-    k_lu<<<dim3(cnt, 1), 1024, 0, s>>>(it, p->ws_d, layer_status, LuBufs{{kBufZ, kBufZ}, {kBufX, kBufX}, 0});
+    launch_lu(dim3(cnt, 1), s, it, p->ws_d, layer_status, p->max_n, LuBufs{{kBufZ, kBufZ}, {kBufX, kBufX}, 0});
     launch_trsm(p->trsm_rows, dim3(xcd_grid(cnt, p->trsm_tiles)), p->trsm_lds, s, it, cnt, p->trsm_tiles, p->ws_d,
                 layer_status, TrsmBufs{{kBufX, kBufX}, {kBufF, kBufF}, {kBufU, kBufU}, 1, 0});  // T (I - X R)^-1
     k_gemm<<<gg, 256, 0, s>>>(it, p->ws_d, kBufU, kBufYS, kBufE, kGemmAccumulate, layer_status);  // R += Y (X T)
@@ -737,7 +737,7 @@ void enqueue_backward(const LaunchSet& ls, const double* tau, const double* omeg
   k_bwd_q<<<dim3((mN * mN + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->layers_d, p->quad_d, dF, p->ws_d, st);
   // U^-T: LU of U^T, right division of the identity
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufX, st);
-  k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, stw, LuBufs{{kBufX, kBufX}, {kBufG, kBufG}, 0});
+  launch_lu(dim3(ni, 1), s, p->items_d, p->ws_d, stw, p->max_n, LuBufs{{kBufX, kBufX}, {kBufG, kBufG}, 0});
   k_fill_identity<<<dim3((mn * mn + 255) / 256, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufF, st);
   launch_trsm(p->trsm_rows, dim3(xcd_grid(ni, p->trsm_tiles)), p->trsm_lds, s, p->items_d, ni, p->trsm_tiles, p->ws_d,
               stw, TrsmBufs{{kBufG, kBufG}, {kBufF, kBufF}, {kBufW, kBufW}, 1, 0});

@@ -222,8 +222,8 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // (v_mfma_f64_16x16x4, rows addressed through the pivot order). P: LDS of at least
 // (n + 1) kLuNb doubles; sL: kLuNb (kLuNb + 1) doubles (L11 at a fixed stride with zeros on and
 // above the diagonal, so that the forward substitution needs no predicate and addresses it by
-// immediate offsets); rv, ri: 32 doubles and 16 ints of LDS. The block
-// is 1024 threads.
+// immediate offsets); rv, ri: 32 doubles and 16 ints of LDS. The block has at least as many
+// threads as the matrix has rows (kLuThreadsBig).
 constexpr int kLuNb = 32;
 static_assert(kLuNb % 4 == 0 && kLuNb <= 64, "panel width: whole MFMA k-steps");
 
@@ -381,9 +381,10 @@ __device__ inline int* lu_perm(double* ex, int n, int which) {
 // transposed into b.dst[side], AT[j n + c] = A(c, j), so that column j of Uu (c < j) and of L
 // (c > j) are contiguous for the right division; pivots and 1 / Uu_kk go to the extras block.
 // The source buffer is overwritten when n > kLdsMaxn (factored in place, in blocked form).
-__global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b) {
+__global__ __launch_bounds__(kLuThreadsLds) void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b) {
   const Item it = items[blockIdx.x];
   if (status[it.layer] != 0) return;
+  if ((it.n > kLdsMaxn) != ((int)blockDim.x == kLuThreadsBig)) return;  // the other launch's systems
   const int n = it.n, tid = threadIdx.x, NT = blockDim.x;
   const int which = blockIdx.y;
   double* base = ws + it.ws;
@@ -423,6 +424,11 @@ __global__ __launch_bounds__(1024) void k_lu(const Item* items, double* ws, int3
     id[i] = invd[i];
     pm[i] = perm[i];
   }
+}
+
+void launch_lu(dim3 grid, hipStream_t s, const Item* items, double* ws, int32_t* status, int max_n, LuBufs b) {
+  k_lu<<<grid, kLuThreadsLds, 0, s>>>(items, ws, status, b);
+  if (max_n > kLdsMaxn) k_lu<<<grid, kLuThreadsBig, 0, s>>>(items, ws, status, b);
 }
 
 // Right division Y = B A^-1 with the factors of k_lu (S' and T' with B = U in the boundary solve,

@@ -348,7 +348,7 @@ void enqueue_beam_outgoing(const LaunchSet& ls, const double* tau, const double*
   gemm(kBufYS, kBufB2, kBufF, 0);                               // Y_S (x_top + x_bot)
   gemm(kBufYT, kBufB3, kBufG, 0);                               // Y_T (x_top - x_bot)
   transpose(kBufU, kBufB2);
-  k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, st, LuBufs{{kBufB2, kBufB2}, {kBufB3, kBufB3}, 0});
+  launch_lu(dim3(ni, 1), s, p->items_d, p->ws_d, st, p->max_n, LuBufs{{kBufB2, kBufB2}, {kBufB3, kBufB3}, 0});
   transpose(kBufF, kBufB2);
   trsm(kBufB3, kBufB2, kBufF);                                  // (U^-1 Y_S x_s)^T
   transpose(kBufG, kBufB2);
@@ -371,7 +371,7 @@ void enqueue_beam_particular(const LaunchSet& ls, const double* omega, const dou
                                                  p->ws_d, st);
   k_gemm<<<gg, 256, 0, s>>>(p->items_d, p->ws_d, kBufF, kBufB0, kBufB1, kGemmAccumulate, st);  // rhs
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufU, kBufB2, st);        // U^T
-  k_lu<<<dim3(ni, 1), 1024, 0, s>>>(p->items_d, p->ws_d, st, LuBufs{{kBufB2, kBufB2}, {kBufB3, kBufB3}, 0});
+  launch_lu(dim3(ni, 1), s, p->items_d, p->ws_d, st, p->max_n, LuBufs{{kBufB2, kBufB2}, {kBufB3, kBufB3}, 0});
   k_transpose<<<dim3(tt, tt, ni), 256, 0, s>>>(p->items_d, p->ws_d, kBufB1, kBufB4, st);       // rhs^T
   launch_trsm(p->trsm_rows, dim3(xcd_grid(ni, p->trsm_tiles)), p->trsm_lds, s, p->items_d, ni, p->trsm_tiles,
               p->ws_d, st, TrsmBufs{{kBufB3, kBufB3}, {kBufB4, kBufB4}, {kBufB2, kBufB2}, 1, 0});  // (U^-1 rhs)^T

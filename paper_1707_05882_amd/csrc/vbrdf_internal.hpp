@@ -174,7 +174,13 @@ __global__ void k_lu32(const Item* items, double* ws, int32_t* status);
 __global__ void k_trsm32(const Item* items, int n_items, int tiles, double* ws, int32_t* status, int accumulate);
 __global__ void k_resid(const Item* items, double* ws, const int32_t* status);
 __global__ void k_bcheck(const Item* items, double* ws, int32_t* status, int no_fallback);
+// k_lu runs twice per factorisation: with kLuThreadsLds threads over the systems held in LDS
+// (n <= kLdsMaxn) and with kLuThreadsBig over the larger, blocked ones (a thread per row);
+// launch_lu issues both (the second only when the plan has such systems).
+constexpr int kLuThreadsLds = 1024, kLuThreadsBig = 512;
+static_assert(kLuThreadsBig >= kMaxn && kLuThreadsBig % 64 == 0, "a thread per row in the blocked LU");
 __global__ void k_lu(const Item* items, double* ws, int32_t* status, LuBufs b);
+void launch_lu(dim3 grid, hipStream_t s, const Item* items, double* ws, int32_t* status, int max_n, LuBufs b);
 // one kernel per tile shape (rows per tile 4, 8 or 16); launch_trsm picks it
 template <int kRows>
 __global__ void k_trsm(const Item* items, int n_items, int tiles, double* ws, int32_t* status, TrsmBufs b);
