@@ -6,22 +6,25 @@
 //
 // Steps (all in FP64):
 //   1. Householder reduction to upper Hessenberg form (the Householder vectors are kept in the
-//      workspace; k_hqapply applies them later, so the orthogonal factor is not accumulated here),
+//      workspace; k_hqapply_mfma / k_hqapply apply them later, so the orthogonal factor is not
+//      accumulated here; blocked, with matrix-core panel updates, for 128 < n <= 256),
 //   2. implicit double-shift (Francis) QR to real Schur form T = Z^T H Z with deflation by the
 //      Ahues-Tisseur criterion, exceptional shifts every 10 stagnant sweeps, a real shift pair
 //      replaced by the eigenvalue closer to the corner used twice, and after 40 stagnant sweeps
 //      (a cluster of nearly equal eigenvalues) a normwise deflation |h| <= ulp ||H||_F,
 //   3. eigenvectors of the quasi-triangular T by back-substitution (complex arithmetic only for
-//      complex pairs), normalised.
+//      complex pairs), normalised; all eigenvectors (n <= 128) or groups of them (n <= 256) advance
+//      together with their columns in LDS.
 // The matrix is not balanced: F E = M^-1 X- M^-1 X+ is graded by the 1/mu factors, and a diagonal
 // power-of-two balancing loses about two digits on its smallest (diffusion-mode) eigenvalues,
 // which dominate the response; without it the eigenpairs reach about 1e-11 relative.
-// The caller then forms U' = Z X_T with a GEMM and U = Q U' with k_hqapply (Q from the
-// Hessenberg reduction). Output convention: for a complex pair stored at
+// The caller then forms U' = Z X_T with a GEMM and U = Q U' with k_hqapply_mfma or k_hqapply (Q
+// from the Hessenberg reduction). Output convention: for a complex pair stored at
 // (j, j+1) with Im lambda_j > 0, U[:, j] + i U[:, j+1] is the eigenvector of lambda_j.
 //
 // H is kept in LDS (row stride n + 1) when n <= 128 and reduced in place in global memory
-// otherwise (the body is instantiated for both, so LDS-resident H uses LDS instructions). A QR
+// otherwise (the body is instantiated for both, so LDS-resident H uses LDS instructions); larger
+// systems chase their multi-bulge passes through an LDS window (windowed_multibulge). A QR
 // sweep touches only a 3-row / 3-column window per bulge step, too little work for a workgroup
 // barrier per step: wave 0 alone runs the deflation scan, the shift choice and the bulge chase,
 // its lanes kept in step by wave-level ordering (every lane computes the reflector itself). The
@@ -429,7 +432,8 @@ __device__ void windowed_multibulge(double* __restrict__ H, int n, double* __res
 // so the only pass over the matrix inside the panel is the product A_0 v_j (read only). After the
 // panel the trailing columns take the whole transformation at once,
 //     X = A_0 - Y V^T,   X <- X - V (W^T X)   (rows p+1..n-1, columns p+nb..n-1),
-// and the rows above the panel (0..p) take the right update A_0 - (A_0 W) V^T. The reflectors are
+// and the rows above the panel (0..p) take the right update A_0 - (A_0 W) V^T, both on the matrix
+// cores. The reflectors are
 // those of the step-by-step reduction (same v_k, tau_k in QV), up to rounding.
 // Used up to kWinMaxN rows, for the reason given there: at n = 512 the blocked form's rounding
 // moves that node cluster's per-order error past what its refinement absorbs (measured 4.6e-9 of
