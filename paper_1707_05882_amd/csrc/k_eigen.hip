@@ -1335,13 +1335,29 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       // then after a barrier from the right to columns k..k+2 of H and Z. Rows of different
       // bulges in a left phase and columns in a right phase are disjoint, and a bulge's
       // reflector input is not touched by the neighbours within a step (gap >= 4).
+      // With H in LDS (n <= 128) the wave's three columns of Z (k..k+2, rows lane and lane + 64)
+      // stay in registers from step to step: after a step, column k is final for this bulge and is
+      // stored, the other two move down, and column k+3 is loaded for the next step (no bulge
+      // touches it in this step: the one ahead works on k+4..k+6, and wrote k+3 in the previous
+      // step). Larger systems update their columns of Z in global memory at every step.
       const int lo = op.lo, hh = op.hh, nb = op.nb, wv = tid >> 6;
       const double* sh = srefl + slot * 3 * kMaxn;
       const int nsteps = (hh - lo) + kMultiGap * (nb - 1);
+      const int zr0 = lane, zr1 = min(lane + 64, n - 1);
+      const bool zv1 = lane + 64 < n;
+      double z00 = 0.0, z01 = 0.0, z02 = 0.0, z10 = 0.0, z11 = 0.0, z12 = 0.0;
       for (int t = 0; t < nsteps; ++t) {
         const int k = lo + t - kMultiGap * wv;
         const bool on = wv < nb && k >= lo && k <= hh - 1;
         const bool three = k < hh - 1;
+        if (kLds && on && k == lo && lane < n) {  // the bulge enters: its first three columns
+          z00 = ZZ(zr0, lo);
+          z01 = ZZ(zr0, lo + 1);
+          z02 = ZZ(zr0, lo + 2);
+          z10 = ZZ(zr1, lo);
+          z11 = ZZ(zr1, lo + 1);
+          z12 = ZZ(zr1, lo + 2);
+        }
         double tau = 0.0, u1 = 0.0, u2 = 0.0, beta = 0.0;
         if (on) {
           double x, y, z;
@@ -1421,12 +1437,22 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               HH(r, k + 1) = h1 - w * u1;
               HH(r, k + 2) = h2 - w * u2;
             }
-            for (int r = lane; r < n; r += 64) {
-              const double z0 = ZZ(r, k), z1 = ZZ(r, k + 1), z2 = ZZ(r, k + 2);
-              const double w = tau * (z0 + u1 * z1 + u2 * z2);
-              ZZ(r, k) = z0 - w;
-              ZZ(r, k + 1) = z1 - w * u1;
-              ZZ(r, k + 2) = z2 - w * u2;
+            if constexpr (kLds) {
+              const double w0 = tau * (z00 + u1 * z01 + u2 * z02), w1 = tau * (z10 + u1 * z11 + u2 * z12);
+              z00 -= w0;
+              z01 -= w0 * u1;
+              z02 -= w0 * u2;
+              z10 -= w1;
+              z11 -= w1 * u1;
+              z12 -= w1 * u2;
+            } else {
+              for (int r = lane; r < n; r += 64) {
+                const double z0 = ZZ(r, k), z1 = ZZ(r, k + 1), z2 = ZZ(r, k + 2);
+                const double w = tau * (z0 + u1 * z1 + u2 * z2);
+                ZZ(r, k) = z0 - w;
+                ZZ(r, k + 1) = z1 - w * u1;
+                ZZ(r, k + 2) = z2 - w * u2;
+              }
             }
           } else {
             for (int r = lane; r <= rmax; r += 64) {
@@ -1435,12 +1461,37 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               HH(r, k) = h0 - w;
               HH(r, k + 1) = h1 - w * u1;
             }
-            for (int r = lane; r < n; r += 64) {
-              const double z0 = ZZ(r, k), z1 = ZZ(r, k + 1);
-              const double w = tau * (z0 + u1 * z1);
-              ZZ(r, k) = z0 - w;
-              ZZ(r, k + 1) = z1 - w * u1;
+            if constexpr (kLds) {
+              const double w0 = tau * (z00 + u1 * z01), w1 = tau * (z10 + u1 * z11);
+              z00 -= w0;
+              z01 -= w0 * u1;
+              z10 -= w1;
+              z11 -= w1 * u1;
+            } else {
+              for (int r = lane; r < n; r += 64) {
+                const double z0 = ZZ(r, k), z1 = ZZ(r, k + 1);
+                const double w = tau * (z0 + u1 * z1);
+                ZZ(r, k) = z0 - w;
+                ZZ(r, k + 1) = z1 - w * u1;
+              }
             }
+          }
+        }
+        if (kLds && on && lane < n) {  // column k is final for this bulge; at its last step column k+1 too
+          ZZ(zr0, k) = z00;
+          if (zv1) ZZ(zr1, k) = z10;
+          if (three) {
+            z00 = z01;
+            z01 = z02;
+            z10 = z11;
+            z11 = z12;
+            if (k + 3 <= hh) {
+              z02 = ZZ(zr0, k + 3);
+              z12 = ZZ(zr1, k + 3);
+            }
+          } else {
+            ZZ(zr0, k + 1) = z01;
+            if (zv1) ZZ(zr1, k + 1) = z11;
           }
         }
         __syncthreads();
