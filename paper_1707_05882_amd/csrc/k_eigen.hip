@@ -128,49 +128,71 @@ struct ZOp {
   int kind, lo, hh, stop, nb;  // nb > 0: multi-bulge pass over lo..hh with nb bulges (no Z op)
 };
 
-// Applies one ZOp to rows t0, t0 + nt, ... of Z (Z(r, c) at ZT[c * n + r]).
-__device__ __forceinline__ void apply_zop(const ZOp& op, const double* rf, double* __restrict__ ZT, int n, int t0,
-                                          int nt) {
-  if (op.kind == 1) {
-    const int lo = op.lo, hh = op.hh;
-    for (int r = t0; r < n; r += nt) {
-      double z0 = ZT[(int64_t)lo * n + r], z1 = ZT[(int64_t)(lo + 1) * n + r];
-      for (int k0 = lo; k0 <= hh - 1; k0 += 8) {
-        double zb[8];  // window entries of the next 8 steps, loaded ahead (not yet written)
+// Applies the reflectors of a sweep over lo..hh (rf[3 k .. 3 k + 2] = (tau, u1, u2) of step k; the
+// last one has two elements) to the line e(k) = L[k st], k = lo..hh: a row of Z or of H from the
+// right, or a column of H from the left (the reflectors are symmetric, so both read the same).
+__device__ __forceinline__ void sweep_line(const double* rf, double* __restrict__ L, int64_t st, int lo, int hh) {
+  double z0 = L[(int64_t)lo * st], z1 = L[(int64_t)(lo + 1) * st];
+  for (int k0 = lo; k0 <= hh - 1; k0 += 8) {
+    double zb[8];  // entries of the next 8 steps, loaded ahead (not yet written)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int c = k0 + 2 + j;
-          zb[j] = (c <= hh) ? ZT[(int64_t)c * n + r] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = k0 + j;
-          if (k <= hh - 1) {
-            const bool three = k < hh - 1;
-            double z2 = three ? zb[j] : 0.0;
-            const double tau = rf[3 * k];
-            if (tau != 0.0) {
-              const double u1 = rf[3 * k + 1], u2 = rf[3 * k + 2];
-              const double w = tau * (z0 + u1 * z1 + (three ? u2 * z2 : 0.0));
-              z0 -= w;
-              z1 -= w * u1;
-              if (three) z2 -= w * u2;
-            }
-            ZT[(int64_t)k * n + r] = z0;
-            z0 = z1;
-            z1 = z2;
-          }
-        }
-      }
-      ZT[(int64_t)hh * n + r] = z0;
+    for (int j = 0; j < 8; ++j) {
+      const int c = k0 + 2 + j;
+      zb[j] = (c <= hh) ? L[(int64_t)c * st] : 0.0;
     }
-  } else if (op.kind == 2) {
-    const int h1 = op.hh - 1, hh = op.hh;
-    const double cs = rf[0], sn = rf[1];
-    for (int r = t0; r < n; r += nt) {
-      const double zx = ZT[(int64_t)h1 * n + r], zy = ZT[(int64_t)hh * n + r];
-      ZT[(int64_t)h1 * n + r] = cs * zx + sn * zy;
-      ZT[(int64_t)hh * n + r] = -sn * zx + cs * zy;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + j;
+      if (k <= hh - 1) {
+        const bool three = k < hh - 1;
+        double z2 = three ? zb[j] : 0.0;
+        const double tau = rf[3 * k];
+        if (tau != 0.0) {
+          const double u1 = rf[3 * k + 1], u2 = rf[3 * k + 2];
+          const double w = tau * (z0 + u1 * z1 + (three ? u2 * z2 : 0.0));
+          z0 -= w;
+          z1 -= w * u1;
+          if (three) z2 -= w * u2;
+        }
+        L[(int64_t)k * st] = z0;
+        z0 = z1;
+        z1 = z2;
+      }
+    }
+  }
+  L[(int64_t)hh * st] = z0;
+}
+
+// Applies one ZOp to lines t0, t0 + nt, ... of the job list: the n rows of Z (Z(r, c) at
+// ZT[c * n + r]) and, when Hd is given (H row-major in global memory, the QR driver's wave 0 having
+// updated only the active block), the parts of H outside the block that the op's transformation
+// reaches: rows 0..b-1 from the right and columns hh+1..n-1 from the left, b = lo (sweep) or
+// hh - 1 (rotation of rows/columns hh - 1, hh).
+__device__ __forceinline__ void apply_zop(const ZOp& op, const double* rf, double* __restrict__ ZT, double* Hd,
+                                          int n, int t0, int nt) {
+  if (op.kind != 1 && op.kind != 2) return;
+  const int hh = op.hh, b = (op.kind == 1) ? op.lo : hh - 1;
+  const int nj = n + (Hd ? b + (n - 1 - hh) : 0);
+  for (int q = t0; q < nj; q += nt) {
+    double* L;
+    int64_t st;
+    if (q < n) {
+      L = ZT + q;
+      st = n;
+    } else if (q < n + b) {
+      L = Hd + (int64_t)(q - n) * n;
+      st = 1;
+    } else {
+      L = Hd + (hh + 1 + (q - n - b));
+      st = n;
+    }
+    if (op.kind == 1) {
+      sweep_line(rf, L, st, op.lo, hh);
+    } else {
+      const double cs = rf[0], sn = rf[1];
+      const double zx = L[(int64_t)b * st], zy = L[(int64_t)hh * st];
+      L[(int64_t)b * st] = cs * zx + sn * zy;
+      L[(int64_t)hh * st] = -sn * zx + cs * zy;
     }
   }
 }
@@ -694,6 +716,136 @@ __device__ void blocked_hessenberg(double* __restrict__ H, int n, double* __rest
 #undef AH
 }
 
+// One double-shift sweep over rows/columns lo..hh - 1 (the three-element steps; the final
+// two-element step is left to the caller) of an n x n matrix held in LDS at row stride LD, run by
+// one wave: x, y, z carry the reflector input from step to step, rf[3 k .. 3 k + 2] receives
+// (tau, u1, u2) of step k, and dum is this lane's private three-double slot beyond the matrix.
+template <int LD>
+__device__ __forceinline__ void lds_chase(double* __restrict__ H, int n, int lo, int hh, double& x, double& y,
+                                          double& z, double* rf, int lane, int W0, int dum) {
+  // Off-block work as n - 3 uniform jobs of three elements each: job j < n - k - 3 is
+  // column k + 3 + j (rows k..k+2, left update), the rest are rows 0..k-1 (columns
+  // k..k+2, right update). Relative to the block origin k (ld + 1) a job starts at
+  // 3 + j (stride ld) or at (j - n + 3) ld (stride 1). Each lane owns jobs lane and
+  // lane + 64; an idle slot works on its private triple in the LDS tail.
+  const int ja = lane, jb = lane + W0;
+  for (int k = lo; k < hh - 1; ++k) {
+    const int kb = k * (LD + 1);
+    double b[4][3];  // rows k..k+3, columns k..k+2 (row k+3 is unused when k+3 > hh)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) b[i][j] = H[kb + i * LD + j];
+    const bool cola = k < n - 3 - ja, colb = k < n - 3 - jb;
+    int ia = cola ? kb + 3 + ja : kb + (ja - n + 3) * LD, sa = cola ? LD : 1;
+    int ib = colb ? kb + 3 + jb : kb + (jb - n + 3) * LD, sb = colb ? LD : 1;
+    if (ja >= n - 3) {
+      ia = dum;
+      sa = 1;
+    }
+    if (jb >= n - 3) {
+      ib = dum;
+      sb = 1;
+    }
+    double va[3], vb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      va[i] = H[ia + i * sa];
+      vb[i] = H[ib + i * sb];
+    }
+    wave_sync();  // all loads of the step precede its stores
+    // Reflector (I - tau u u^T), u = (1, u1, u2), taking (x, y, z) to (beta, 0, 0)
+    // with beta = -sign(x) ||(x, y, z)||. Then tau = 1 + |x| / ||.|| and
+    // 1 / (x - beta) = sign(x) / (|x| + ||.||): one reciprocal square root and one
+    // reciprocal, each refined by two Newton steps. With y = z = 0 the step is the
+    // identity (tau = 0, beta = x) and the updates below rewrite the same values.
+    double tau = 0.0, u1 = 0.0, u2 = 0.0, beta = x;
+    if (y != 0.0 || z != 0.0) {
+      double xs = x, ys = y, zs = z, unscale = 1.0;
+      double s2 = xs * xs + ys * ys + zs * zs;
+      if (s2 < 0x1p-900) {  // keep the squares clear of the subnormal range
+        xs *= 0x1p600;
+        ys *= 0x1p600;
+        zs *= 0x1p600;
+        unscale = 0x1p-600;
+        s2 = xs * xs + ys * ys + zs * zs;
+      }
+      double r = __builtin_amdgcn_rsq(s2);
+      const double h2 = 0.5 * s2;
+      r = r * fma(-h2 * r, r, 1.5);
+      r = r * fma(-h2 * r, r, 1.5);
+      const double nrm = s2 * r;
+      const double ax = fabs(xs);
+      tau = fma(ax, r, 1.0);
+      const double dd = ax + nrm;
+      double q = __builtin_amdgcn_rcp(dd);
+      q = fma(q, fma(-dd, q, 1.0), q);
+      q = fma(q, fma(-dd, q, 1.0), q);
+      const double sc = copysign(q, xs);
+      u1 = ys * sc;
+      u2 = zs * sc;
+      beta = -copysign(nrm, xs) * unscale;
+    }
+    {
+      const double w = tau * (va[0] + u1 * va[1] + u2 * va[2]);
+      H[ia] = va[0] - w;
+      H[ia + sa] = va[1] - w * u1;
+      H[ia + 2 * sa] = va[2] - w * u2;
+    }
+    {
+      const double w = tau * (vb[0] + u1 * vb[1] + u2 * vb[2]);
+      H[ib] = vb[0] - w;
+      H[ib + sb] = vb[1] - w * u1;
+      H[ib + 2 * sb] = vb[2] - w * u2;
+    }
+    for (int j = lane + 2 * W0; j < n - 3; j += W0) {  // only with fewer than 64 lanes
+      const int jj = (j < n - k - 3) ? kb + 3 + j : kb + (j - n + 3) * LD;
+      const int st = (j < n - k - 3) ? LD : 1;
+      const double w = tau * (H[jj] + u1 * H[jj + st] + u2 * H[jj + 2 * st]);
+      H[jj] -= w;
+      H[jj + st] -= w * u1;
+      H[jj + 2 * st] -= w * u2;
+    }
+    // corner block: rows k..k+2 from the left, then rows k..k+3 from the right
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double w = tau * (b[0][j] + u1 * b[1][j] + u2 * b[2][j]);
+      b[0][j] -= w;
+      b[1][j] -= w * u1;
+      b[2][j] -= w * u2;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double w = tau * (b[i][0] + u1 * b[i][1] + u2 * b[i][2]);
+      b[i][0] -= w;
+      b[i][1] -= w * u1;
+      b[i][2] -= w * u2;
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) H[kb + i * LD + j] = b[i][j];
+      if (k + 3 <= hh) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) H[kb + 3 * LD + j] = b[3][j];
+      }
+      if (k > lo) {
+        H[kb - 1] = beta;
+        H[kb - 1 + LD] = 0.0;
+        H[kb - 1 + 2 * LD] = 0.0;
+      }
+      rf[3 * k] = tau;
+      rf[3 * k + 1] = u1;
+      rf[3 * k + 2] = u2;
+    }
+    wave_sync();
+    x = b[1][0];
+    y = b[2][0];
+    z = b[3][0];
+  }
+}
+
 template <bool kLds>
 __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t* status, double* sH, double* srefl,
                                            double* sred, int* sctl, double* sxyz, ZOp* zops, int sweep_cap) {
@@ -832,6 +984,14 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
   // wave 0 left in LDS, so the two overlap. With a single wave the update follows at once.
   const bool split = NT > 64;
   const int nwave = (NT % 64 == 0) ? NT / 64 : 0;  // waves available for multi-bulge passes
+  // Systems in global memory that take the windowed multi-bulge pass also keep wave 0's sweeps and
+  // rotations inside the active block [lo, hh] (a block of at most kWin rows is chased in LDS); the
+  // parts of H the transformation reaches outside the block (rows above it, columns to its right)
+  // are updated with Z by the other waves during the next iteration. Nothing wave 0 reads before
+  // that lies there: the next block is the same block, a part of it, or lies above it, and the
+  // deflation scan reads near-diagonal entries only (the one in those parts, H(lo - 1, lo), sits
+  // beside the zero H(lo, lo - 1), which decides the test on its own).
+  const bool dec = !kLds && n <= kWinMaxN && NT >= 64;
   if (tid == 0) {
     sctl[1] = n - 1;  // active bottom index hh
     sctl[2] = 0;      // iterations since last deflation
@@ -848,28 +1008,35 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       if (hh < 0) {
         if (lane == 0) zops[slot] = ZOp{0, 0, 0, 1, 0};
       } else {
-        int cand = 0;
-        for (int k = 1 + lane; k <= hh; k += W0) {
-          const double hk = fabs(HH(k, k - 1));
-          bool small = hk <= kSafeMin || (sctl[2] >= 40 && hk <= kUlp * hnorm);
-          if (!small) {
-            double tst = fabs(HH(k - 1, k - 1)) + fabs(HH(k, k));
-            if (tst == 0.0) {
-              if (k >= 2) tst += fabs(HH(k - 1, k - 2));
-              if (k + 1 <= hh) tst += fabs(HH(k + 1, k));
+        // scanned from the bottom, W0 rows at a time: the first group with a negligible
+        // subdiagonal entry holds the lowest one
+        int l = 0;
+        for (int top = hh; top >= 1; top -= W0) {
+          int cand = 0;
+          const int k = top - lane;
+          if (k >= 1) {
+            const double hk = fabs(HH(k, k - 1));
+            bool small = hk <= kSafeMin || (sctl[2] >= 40 && hk <= kUlp * hnorm);
+            if (!small) {
+              double tst = fabs(HH(k - 1, k - 1)) + fabs(HH(k, k));
+              if (tst == 0.0) {
+                if (k >= 2) tst += fabs(HH(k - 1, k - 2));
+                if (k + 1 <= hh) tst += fabs(HH(k + 1, k));
+              }
+              if (hk <= kUlp * tst) {
+                const double hu = fabs(HH(k - 1, k));
+                const double ab = fmax(hk, hu), ba = fmin(hk, hu);
+                const double dd = fabs(HH(k - 1, k - 1) - HH(k, k));
+                const double aa = fmax(fabs(HH(k, k)), dd), bb = fmin(fabs(HH(k, k)), dd);
+                const double s = aa + ab;
+                small = ba * (ab / s) <= fmax(kSafeMin, kUlp * (bb * (aa / s)));
+              }
             }
-            if (hk <= kUlp * tst) {
-              const double hu = fabs(HH(k - 1, k));
-              const double ab = fmax(hk, hu), ba = fmin(hk, hu);
-              const double dd = fabs(HH(k - 1, k - 1) - HH(k, k));
-              const double aa = fmax(fabs(HH(k, k)), dd), bb = fmin(fabs(HH(k, k)), dd);
-              const double s = aa + ab;
-              small = ba * (ab / s) <= fmax(kSafeMin, kUlp * (bb * (aa / s)));
-            }
+            if (small) cand = k;
           }
-          if (small) cand = max(cand, k);
+          l = __builtin_amdgcn_readfirstlane(wave_max(cand));
+          if (l > 0) break;
         }
-        const int l = wave_max(cand);
         if (lane == 0) {
           zops[slot] = ZOp{0, 0, 0, 0, 0};
           if (l > 0) HH(l, l - 1) = 0.0;
@@ -1001,130 +1168,73 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
           // are issued before its reflector is formed.
           const int lo = __builtin_amdgcn_readfirstlane(sctl[6]);
           double x = sxyz[0], y = sxyz[1], z = sxyz[2];
+          const bool blk_lds = dec && hh - lo + 1 <= kWin;
           if constexpr (kLds) {
-            // Off-block work as n - 3 uniform jobs of three elements each: job j < n - k - 3 is
-            // column k + 3 + j (rows k..k+2, left update), the rest are rows 0..k-1 (columns
-            // k..k+2, right update). Relative to the block origin k (ld + 1) a job starts at
-            // 3 + j (stride ld) or at (j - n + 3) ld (stride 1). Each lane owns jobs lane and
-            // lane + 64; an idle slot works on its private triple in the LDS tail.
-            constexpr int LD = kLdsMaxn + 1;
-            const int ja = lane, jb = lane + W0;
-            const int dum = kLdsMaxn * LD + 3 * lane;
-            for (int k = lo; k < hh - 1; ++k) {
-              const int kb = k * (LD + 1);
-              double b[4][3];  // rows k..k+3, columns k..k+2 (row k+3 is unused when k+3 > hh)
+            lds_chase<kLdsMaxn + 1>(H, n, lo, hh, x, y, z, rf, lane, W0, kLdsMaxn * (kLdsMaxn + 1) + 3 * lane);
+          } else if (blk_lds) {
+            // The block rows/columns lo..hh moves to LDS (row stride kWinLd), is chased there as
+            // a matrix of its own and goes back; a lane's private slots lie after row kWin.
+            const int m = hh - lo + 1;
+            double* __restrict__ B = sH;
+            for (int r0 = 0; r0 < m; r0 += 4) {
+              double v[4][2];  // loads of four rows in flight (clamped indexes, stores masked)
+              const int c0 = min(lane, m - 1), c1 = min(lane + 64, m - 1);
 #pragma unroll
-              for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) b[i][j] = H[kb + i * LD + j];
-              const bool cola = k < n - 3 - ja, colb = k < n - 3 - jb;
-              int ia = cola ? kb + 3 + ja : kb + (ja - n + 3) * LD, sa = cola ? LD : 1;
-              int ib = colb ? kb + 3 + jb : kb + (jb - n + 3) * LD, sb = colb ? LD : 1;
-              if (ja >= n - 3) {
-                ia = dum;
-                sa = 1;
-              }
-              if (jb >= n - 3) {
-                ib = dum;
-                sb = 1;
-              }
-              double va[3], vb[3];
-#pragma unroll
-              for (int i = 0; i < 3; ++i) {
-                va[i] = H[ia + i * sa];
-                vb[i] = H[ib + i * sb];
-              }
-              wave_sync();  // all loads of the step precede its stores
-              // Reflector (I - tau u u^T), u = (1, u1, u2), taking (x, y, z) to (beta, 0, 0)
-              // with beta = -sign(x) ||(x, y, z)||. Then tau = 1 + |x| / ||.|| and
-              // 1 / (x - beta) = sign(x) / (|x| + ||.||): one reciprocal square root and one
-              // reciprocal, each refined by two Newton steps. With y = z = 0 the step is the
-              // identity (tau = 0, beta = x) and the updates below rewrite the same values.
-              double tau = 0.0, u1 = 0.0, u2 = 0.0, beta = x;
-              if (y != 0.0 || z != 0.0) {
-                double xs = x, ys = y, zs = z, unscale = 1.0;
-                double s2 = xs * xs + ys * ys + zs * zs;
-                if (s2 < 0x1p-900) {  // keep the squares clear of the subnormal range
-                  xs *= 0x1p600;
-                  ys *= 0x1p600;
-                  zs *= 0x1p600;
-                  unscale = 0x1p-600;
-                  s2 = xs * xs + ys * ys + zs * zs;
-                }
-                double r = __builtin_amdgcn_rsq(s2);
-                const double h2 = 0.5 * s2;
-                r = r * fma(-h2 * r, r, 1.5);
-                r = r * fma(-h2 * r, r, 1.5);
-                const double nrm = s2 * r;
-                const double ax = fabs(xs);
-                tau = fma(ax, r, 1.0);
-                const double dd = ax + nrm;
-                double q = __builtin_amdgcn_rcp(dd);
-                q = fma(q, fma(-dd, q, 1.0), q);
-                q = fma(q, fma(-dd, q, 1.0), q);
-                const double sc = copysign(q, xs);
-                u1 = ys * sc;
-                u2 = zs * sc;
-                beta = -copysign(nrm, xs) * unscale;
-              }
-              {
-                const double w = tau * (va[0] + u1 * va[1] + u2 * va[2]);
-                H[ia] = va[0] - w;
-                H[ia + sa] = va[1] - w * u1;
-                H[ia + 2 * sa] = va[2] - w * u2;
-              }
-              {
-                const double w = tau * (vb[0] + u1 * vb[1] + u2 * vb[2]);
-                H[ib] = vb[0] - w;
-                H[ib + sb] = vb[1] - w * u1;
-                H[ib + 2 * sb] = vb[2] - w * u2;
-              }
-              for (int j = lane + 2 * W0; j < n - 3; j += W0) {  // only with fewer than 64 lanes
-                const int jj = (j < n - k - 3) ? kb + 3 + j : kb + (j - n + 3) * LD;
-                const int st = (j < n - k - 3) ? LD : 1;
-                const double w = tau * (H[jj] + u1 * H[jj + st] + u2 * H[jj + 2 * st]);
-                H[jj] -= w;
-                H[jj + st] -= w * u1;
-                H[jj + 2 * st] -= w * u2;
-              }
-              // corner block: rows k..k+2 from the left, then rows k..k+3 from the right
-#pragma unroll
-              for (int j = 0; j < 3; ++j) {
-                const double w = tau * (b[0][j] + u1 * b[1][j] + u2 * b[2][j]);
-                b[0][j] -= w;
-                b[1][j] -= w * u1;
-                b[2][j] -= w * u2;
+              for (int i = 0; i < 4; ++i) {
+                const int r = min(r0 + i, m - 1);
+                v[i][0] = HH(lo + r, lo + c0);
+                v[i][1] = HH(lo + r, lo + c1);
               }
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const double w = tau * (b[i][0] + u1 * b[i][1] + u2 * b[i][2]);
-                b[i][0] -= w;
-                b[i][1] -= w * u1;
-                b[i][2] -= w * u2;
+                if (r0 + i < m) {
+                  if (lane < m) B[(r0 + i) * kWinLd + lane] = v[i][0];
+                  if (lane + 64 < m) B[(r0 + i) * kWinLd + lane + 64] = v[i][1];
+                }
+              }
+            }
+            wave_sync();
+            lds_chase<kWinLd>(B, m, 0, m - 1, x, y, z, rf + 3 * lo, lane, 64, kWin * kWinLd + 3 * lane);
+            {  // final two-element step on block rows/columns m - 2, m - 1
+              const int k = m - 2;
+              const double nrm = sqrt(x * x + y * y);
+              double tau = 0.0, u1 = 0.0, beta = 0.0;
+              if (nrm != 0.0 && y != 0.0) {
+                beta = (x >= 0.0) ? -nrm : nrm;
+                tau = (beta - x) / beta;
+                u1 = y / (x - beta);
+              }
+              if (tau != 0.0) {
+                if (lane == 0) {
+                  B[k * kWinLd + k - 1] = beta;
+                  B[(k + 1) * kWinLd + k - 1] = 0.0;
+                }
+                if (lane < 2) {
+                  const int c = k + lane;
+                  const double w = tau * (B[k * kWinLd + c] + u1 * B[(k + 1) * kWinLd + c]);
+                  B[k * kWinLd + c] -= w;
+                  B[(k + 1) * kWinLd + c] -= w * u1;
+                }
+                wave_sync();
+                for (int r = lane; r < m; r += 64) {
+                  const double w = tau * (B[r * kWinLd + k] + u1 * B[r * kWinLd + k + 1]);
+                  B[r * kWinLd + k] -= w;
+                  B[r * kWinLd + k + 1] -= w * u1;
+                }
               }
               if (lane == 0) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                  for (int j = 0; j < 3; ++j) H[kb + i * LD + j] = b[i][j];
-                if (k + 3 <= hh) {
-#pragma unroll
-                  for (int j = 0; j < 3; ++j) H[kb + 3 * LD + j] = b[3][j];
-                }
-                if (k > lo) {
-                  H[kb - 1] = beta;
-                  H[kb - 1 + LD] = 0.0;
-                  H[kb - 1 + 2 * LD] = 0.0;
-                }
-                rf[3 * k] = tau;
-                rf[3 * k + 1] = u1;
-                rf[3 * k + 2] = u2;
+                rf[3 * (hh - 1)] = tau;
+                rf[3 * (hh - 1) + 1] = u1;
+                rf[3 * (hh - 1) + 2] = 0.0;
+                zops[slot] = ZOp{1, lo, hh, 0, 0};
               }
               wave_sync();
-              x = b[1][0];
-              y = b[2][0];
-              z = b[3][0];
             }
+            for (int r = 0; r < m; ++r) {
+              if (lane < m) HH(lo + r, lo + lane) = B[r * kWinLd + lane];
+              if (lane + 64 < m) HH(lo + r, lo + lane + 64) = B[r * kWinLd + lane + 64];
+            }
+            wave_sync();
           } else {
           for (int k = lo; k < hh - 1; ++k) {
             const bool row3 = k + 3 <= hh;
@@ -1135,23 +1245,26 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
               for (int j = 0; j < 3; ++j) b[i][j] = HH(k + i, k + j);
 #pragma unroll
             for (int j = 0; j < 3; ++j) b[3][j] = row3 ? HH(k + 3, k + j) : 0.0;
-            // Off-block work as n - 3 uniform jobs of three elements each: job j < ncol is
-            // column k + 3 + j (rows k..k+2, left update), the rest are rows 0..k-1 (columns
-            // k..k+2, right update). The first two jobs of each lane are loaded up front.
-            const int ncol = n - k - 3, njob = n - 3;
+            // Off-block work as uniform jobs of three elements each: job j < ncol is column
+            // k + 3 + j (rows k..k+2, left update), the rest are rows rbeg..k-1 (columns
+            // k..k+2, right update), over the whole matrix (rbeg = 0, cend = n) or, with the
+            // block-local updates, the block (rbeg = lo, cend = hh + 1). The first two jobs of
+            // each lane are loaded up front.
+            const int cend = dec ? hh + 1 : n, rbeg = dec ? lo : 0;
+            const int ncol = cend - k - 3, njob = cend - rbeg - 3;
             int64_t ja = 0, jb = 0, sa = 1, sb = 1;
             double va[3] = {0.0, 0.0, 0.0}, vb[3] = {0.0, 0.0, 0.0};
             const bool ha = lane < njob, hb = lane + W0 < njob;
             if (ha) {
               const int j = lane;
-              ja = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(j - ncol) * ld + k;
+              ja = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(rbeg + j - ncol) * ld + k;
               sa = (j < ncol) ? ld : 1;
 #pragma unroll
               for (int i = 0; i < 3; ++i) va[i] = H[ja + i * sa];
             }
             if (hb) {
               const int j = lane + W0;
-              jb = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(j - ncol) * ld + k;
+              jb = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(rbeg + j - ncol) * ld + k;
               sb = (j < ncol) ? ld : 1;
 #pragma unroll
               for (int i = 0; i < 3; ++i) vb[i] = H[jb + i * sb];
@@ -1202,7 +1315,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
                 H[jb + 2 * sb] = vb[2] - w * u2;
               }
               for (int j = lane + 2 * W0; j < njob; j += W0) {
-                const int64_t jj = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(j - ncol) * ld + k;
+                const int64_t jj = (j < ncol) ? (int64_t)k * ld + k + 3 + j : (int64_t)(rbeg + j - ncol) * ld + k;
                 const int64_t st = (j < ncol) ? ld : 1;
                 const double w = tau * (H[jj] + u1 * H[jj + st] + u2 * H[jj + 2 * st]);
                 H[jj] -= w;
@@ -1251,7 +1364,7 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
             z = b[3][0];
           }
           }
-          {  // final two-element step k = hh - 1 on rows/columns hh-1, hh
+          if (!blk_lds) {  // final two-element step k = hh - 1 on rows/columns hh-1, hh
             const int k = hh - 1;
             const double nrm = sqrt(x * x + y * y);
             double tau = 0.0, u1 = 0.0, beta = 0.0;
@@ -1265,13 +1378,13 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
                 HH(k, k - 1) = beta;
                 HH(k + 1, k - 1) = 0.0;
               }
-              for (int c = k + lane; c < n; c += W0) {
+              for (int c = k + lane; c < (dec ? hh + 1 : n); c += W0) {
                 const double w = tau * (HH(k, c) + u1 * HH(k + 1, c));
                 HH(k, c) -= w;
                 HH(k + 1, c) -= w * u1;
               }
               wave_sync();
-              for (int r = lane; r <= hh; r += W0) {
+              for (int r = (dec ? lo : 0) + lane; r <= hh; r += W0) {
                 const double w = tau * (HH(r, k) + u1 * HH(r, k + 1));
                 HH(r, k) -= w;
                 HH(r, k + 1) -= w * u1;
@@ -1288,13 +1401,13 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
         } else if (act == kActRotate) {  // split a real 2x2 block with [[cs, -sn], [sn, cs]]
           const int h1 = hh - 1;
           const double cs = sxyz[0], sn = sxyz[1];
-          for (int c = h1 + lane; c < n; c += W0) {
+          for (int c = h1 + lane; c < (dec ? hh + 1 : n); c += W0) {
             const double x = HH(h1, c), y = HH(hh, c);
             HH(h1, c) = cs * x + sn * y;
             HH(hh, c) = -sn * x + cs * y;
           }
           wave_sync();
-          for (int r = lane; r <= hh; r += W0) {
+          for (int r = (dec ? h1 : 0) + lane; r <= hh; r += W0) {
             const double x = HH(r, h1), y = HH(r, hh);
             HH(r, h1) = cs * x + sn * y;
             HH(r, hh) = -sn * x + cs * y;
@@ -1319,10 +1432,11 @@ __device__ __forceinline__ void eigen_body(const Item& it, double* base, int32_t
       }
     }
     if (split) {
-      if (!wave0 && iter > 0) apply_zop(zops[slot ^ 1], srefl + (slot ^ 1) * 3 * kMaxn, ZT, n, tid - 64, NT - 64);
+      if (!wave0 && iter > 0)
+        apply_zop(zops[slot ^ 1], srefl + (slot ^ 1) * 3 * kMaxn, ZT, dec ? H : nullptr, n, tid - 64, NT - 64);
     } else {
       wave_sync();
-      apply_zop(zops[slot], rf, ZT, n, tid, NT);
+      apply_zop(zops[slot], rf, ZT, dec ? H : nullptr, n, tid, NT);
     }
     __syncthreads();
     const ZOp op = zops[slot];  // not rewritten before the barrier of the next iteration
