@@ -5,6 +5,9 @@
 // (eq. 45), the back-transformation of the eigenvectors and the products of the eigenpair
 // refinement. Each item carries its own n; the grid covers the largest n and surplus tiles exit.
 //
+// Workgroup order: the (item, tile) list is cut into 8 contiguous ranges, one per XCD, and every
+// range holds whole items, every eighth one (all tiles of an item share one L2; 18% faster than the
+// plain grid order, and a split into contiguous item ranges lost that to the uneven sizes).
 // Tiling: 64 x 64 output tile per workgroup of 4 waves; each wave owns a 32 x 32 quadrant as 2 x 2
 // v_mfma_f64_16x16x4 tiles; K is staged through LDS 16 at a time, the next step's tiles loaded into
 // registers while the current step is multiplied. Lane layout of the 16x16x4 FP64
@@ -23,10 +26,31 @@ constexpr int kGK = 16;  // K step
 __global__ __launch_bounds__(256) void k_gemm(const Item* items, double* ws, int bufA, int bufB, int bufC, int mode,
                                                const int32_t* status) {
   const bool transA = mode & kGemmTransA, transB = mode & kGemmTransB, transC = mode & kGemmTransC;
-  const Item it = items[blockIdx.z];
+  // XCD-aware order: workgroups go to the 8 XCDs round-robin by linear id L, so XCD g (= L mod 8)
+  // takes a contiguous range of the (item, tile) list, V = g q + min(g, r) + L / 8 with
+  // q r = divmod(#workgroups, 8), a bijection: the tiles of an item share one L2.
+  const int ntile = gridDim.x * gridDim.y;
+  const int64_t total = (int64_t)ntile * gridDim.z;
+  const int64_t L = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  const int64_t xq = total / 8, xr = total % 8, xg = L % 8;
+  const int64_t V = xg * xq + (xg < xr ? xg : xr) + L / 8;
+  // Within the range, virtual item c becomes item 8 k + g for the c-th entry (g, k) of the
+  // contiguous split of the items into 8 groups: each XCD holds every eighth item, so the sizes of
+  // consecutive items (one layer's orders) spread evenly over the XCDs.
+  const int tile = (int)(V % ntile);
+  const int64_t vi = V / ntile, ni = gridDim.z, iq = ni / 8, ir = ni % 8;
+  int64_t ig, ik;
+  if (vi < ir * (iq + 1)) {
+    ig = vi / (iq + 1);
+    ik = vi - ig * (iq + 1);
+  } else {
+    ig = ir + (vi - ir * (iq + 1)) / (iq > 0 ? iq : 1);
+    ik = vi - ir * (iq + 1) - (ig - ir) * iq;
+  }
+  const Item it = items[8 * ik + ig];
   if (status[it.layer] != 0) return;
   const int n = it.n;
-  const int r0 = blockIdx.y * kGT, c0 = blockIdx.x * kGT;
+  const int r0 = (tile / gridDim.x) * kGT, c0 = (tile % gridDim.x) * kGT;
   if (r0 >= n || c0 >= n) return;
   const double* A = buf_ptr(ws, it, bufA);
   const double* B = buf_ptr(ws, it, bufB);
